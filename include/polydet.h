@@ -1,0 +1,182 @@
+/*
+ * polydet: exact determinants of matrices of multivariate integer polynomials on MI355X.
+ *
+ * The operation is the one of Wei & Chen, "Optimized Multivariate Polynomial Determinant
+ * on GPU" (arXiv 2010.12117), Algorithm 1: for an n x n matrix M whose entries are
+ * polynomials in x1..xk with integer coefficients, return det M in Z[x1..xk] exactly.
+ * The method is modular (Section 2): for each word-size prime p with a large power-of-two
+ * root of unity (equation "primes"), every entry is evaluated on a grid of roots of unity
+ * (FFT), a determinant is taken at every grid point over Z/pZ (DET, the role of
+ * Algorithm 3), the determinant polynomial mod p is interpolated (IFFT, Section 3.3), and
+ * the integer coefficients are rebuilt by mixed-radix conversion (CRT, Section 3.4 and
+ * Algorithm 4).
+ *
+ * Conventions of this interface
+ * -----------------------------
+ * Input coefficients: int64, C order [n][n][deg[0]+1]...[deg[k-1]+1]. Entry (i, j) is the
+ *   dense coefficient box of a polynomial, first variable slowest, exactly the encoding of
+ *   Section 2's worked example (F = 1 + 2x + 3xy + 4x^2 + 5y^2 -> [1,0,5,2,3,0,4,0,0]).
+ *   Any int64 is accepted, INT64_MIN included. nvars = 0 means an integer matrix.
+ * Degree bound: D[v] = n * deg[v], an upper bound on the determinant's degree in x_v.
+ * Grid: N[v] = next power of two >= D[v] + 1 (the paper rounds degrees up to powers of two,
+ *   Section 2; interpolation needs D[v] + 1 distinct nodes, Theorem 1), G = prod N[v].
+ * Primes: p in (2^30, 2^31) with p = 1 mod 2^16, in descending order ("9-digit" primes
+ *   of the form c * 2^q + 1, Section 2). The count pn is the least with
+ *   (p_0 ... p_{pn-1})^2 > 4 B^2, where B^2 = min(prod_i sum_j |a_ij|_1^2,
+ *   prod_j sum_i |a_ij|_1^2) bounds the squared coefficients of det M (Hadamard's
+ *   inequality on 1-norms; the paper says only that the bound is easily computed).
+ * Output: uint32 limbs [D[0]+1]...[D[k-1]+1][limbs], coefficient of x^e at the multi-index
+ *   e (first variable slowest), each coefficient a little-endian two's-complement integer
+ *   of `limbs` 32-bit words, recovered in the symmetric range (-(M-1)/2, (M-1)/2] with
+ *   M = p_0 ... p_{pn-1}. Coefficients above the true degree are zero.
+ *
+ * Ownership: the caller owns coefficient, output and workspace buffers (device memory
+ *   unless stated). A plan owns its device constant tables (allocated by polydet_plan*,
+ *   freed by polydet_plan_destroy). Plans are immutable after creation; solves on one plan
+ *   may run concurrently on different streams when each has its own workspace and output.
+ * Errors: argument and shape errors return synchronously and enqueue nothing. Solves are
+ *   asynchronous on `stream`; a launch failure returns POLYDET_EDEVICE, a later device
+ *   fault shows at the caller's stream synchronisation. polydet_last_error() returns a
+ *   message for the calling thread's last failure.
+ */
+#ifndef POLYDET_H
+#define POLYDET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum polydet_status {
+  POLYDET_OK = 0,
+  POLYDET_EINVAL = 1,        /* bad argument, shape or buffer size */
+  POLYDET_EUNSUPPORTED = 2,  /* beyond this build's limits (see polydet_limits) */
+  POLYDET_ENOMEM = 3,        /* host or device allocation failed */
+  POLYDET_EDEVICE = 4,       /* HIP error; message in polydet_last_error() */
+  POLYDET_ECANCELLED = 5
+} polydet_status;
+
+#define POLYDET_MAX_VARS 8
+
+/* Shape of one matrix. coeff_bits: every |coefficient| <= 2^coeff_bits (0..63); used for
+ * the worst-case bound when a plan is made without the coefficients. */
+typedef struct polydet_shape {
+  int32_t n;
+  int32_t nvars;
+  int32_t deg[POLYDET_MAX_VARS];
+  int32_t coeff_bits;
+} polydet_shape;
+
+/* Plan flags. POLYDET_FORCE_PN(x): use exactly x primes (x >= the number the bound needs,
+ * else EINVAL). POLYDET_PRIME_OFFSET(x): skip the first x primes of the table (a disjoint
+ * prime set; the result does not depend on it). */
+#define POLYDET_FORCE_PN(x) ((uint32_t)((x) & 0xFFF) << 8)
+/* POLYDET_DET_LANES_LOG2(x): 2^x lanes cooperate on one determinant (x in 0..4) instead
+ * of the default for the order; EUNSUPPORTED if no kernel is compiled for that pair. */
+#define POLYDET_DET_LANES_LOG2(x) ((uint32_t)(((x) + 1) & 0xF) << 4)
+#define POLYDET_PRIME_OFFSET(x) ((uint32_t)((x) & 0x3FF) << 20)
+/* POLYDET_HOST_ONLY: compute the plan on the host and upload nothing (no GPU needed); the
+ * plan can be queried but not solved (polydet_solve* return EINVAL). */
+#define POLYDET_HOST_ONLY ((uint32_t)1u << 31)
+/* POLYDET_STAGE_TIMING: every solve of the plan records HIP events on its stream around
+ * each stage (read by polydet_stage_times). Solves of such a plan must not overlap. */
+#define POLYDET_STAGE_TIMING ((uint32_t)1u << 30)
+
+#define POLYDET_NUM_STAGES 5 /* reduce, evaluate, determinants, interpolate, reconstruct */
+
+/* What a plan needs and produces. Workspace offsets (bytes) locate the intermediate stages
+ * for inspection after a solve on the same stream has completed:
+ *   off_eval : uint32 [pn][n*n][G]  entry values at the grid points, Montgomery form
+ *              (x * 2^32 mod p); point index = natural multi-index (j_1 slowest), node
+ *              (w_1^j_1, ..., w_k^j_k) with w_v = g^((p-1)/N[v]), g the least primitive
+ *              root mod p;
+ *   off_detv : uint32 [pn][G]        determinant at each grid point, Montgomery form;
+ *   off_coef : uint32 [pn][ncoeff]   coefficients of det M mod p, Montgomery form. */
+typedef struct polydet_plan_info {
+  int32_t n, nvars;
+  int32_t deg[POLYDET_MAX_VARS];
+  int32_t D[POLYDET_MAX_VARS];
+  int32_t N[POLYDET_MAX_VARS];
+  int64_t G;          /* grid points per prime */
+  int64_t ncoeff;     /* prod (D[v] + 1): output coefficients */
+  int64_t nterms;     /* prod (deg[v] + 1): input coefficients per entry */
+  int32_t pn;         /* primes */
+  int32_t limbs;      /* 32-bit limbs per output coefficient */
+  int32_t det_lanes;  /* lanes that cooperate on one determinant */
+  int32_t reserved;
+  size_t in_bytes;    /* 8 * n * n * nterms */
+  size_t out_bytes;   /* 4 * ncoeff * limbs */
+  size_t workspace_bytes;
+  size_t off_eval, off_detv, off_coef;
+} polydet_plan_info;
+
+typedef struct polydet_plan_s* polydet_plan_t;
+
+/* Build a plan for one matrix shape.
+ * host_coeffs: NULL, or the int64 coefficients on the host in the input layout; with them
+ *   the bound B is computed from the data (fewer primes), without them from coeff_bits.
+ *   Only pn and limbs depend on this choice; the coefficients of the result do not.
+ * Returns EINVAL for n < 1, nvars outside 0..8, a negative degree or coeff_bits outside
+ * 0..63; EUNSUPPORTED beyond polydet_limits; EDEVICE/ENOMEM when uploading tables fails.
+ * The plan's tables live on the device that is current when it is built. */
+polydet_status polydet_plan(const polydet_shape* shape, const int64_t* host_coeffs,
+                            uint32_t flags, polydet_plan_t* out);
+
+/* Build one plan for `count` matrices of possibly different shapes, solved together by
+ * polydet_solve_batch. host_coeffs: NULL or an array of `count` host pointers (each may be
+ * NULL). Index i of polydet_plan_query refers to matrix i. */
+polydet_status polydet_plan_batch(const polydet_shape* shapes, int32_t count,
+                                  const int64_t* const* host_coeffs, uint32_t flags,
+                                  polydet_plan_t* out);
+
+/* Plan information; for a batch plan `index` selects the matrix (0 for a single plan). For
+ * a batch plan, workspace_bytes is the workspace of the whole batch. */
+polydet_status polydet_plan_query(polydet_plan_t plan, int32_t index, polydet_plan_info* out);
+
+/* The primes of matrix `index` (host array of at least pn entries). */
+polydet_status polydet_plan_primes(polydet_plan_t plan, int32_t index, uint32_t* out,
+                                   int32_t capacity);
+
+/* Solve one matrix (plan made by polydet_plan).
+ * d_coeffs: device int64 coefficients (in_bytes); d_out: device uint32 limbs (out_bytes);
+ * d_workspace: device scratch of at least workspace_bytes, 256-byte aligned; stream: a
+ * hipStream_t (NULL = the default stream). Asynchronous. */
+polydet_status polydet_solve(polydet_plan_t plan, const int64_t* d_coeffs, uint32_t* d_out,
+                             void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* Solve every matrix of a batch plan.
+ * d_coeffs: device int64 buffer holding every matrix's coefficients; coeff_offsets[i]
+ * (host, in int64 elements) is where matrix i starts. d_out: device uint32 buffer;
+ * out_offsets[i] (host, in uint32 elements) is where matrix i's limbs start. Outputs of
+ * different matrices must not overlap. */
+polydet_status polydet_solve_batch(polydet_plan_t plan, const int64_t* d_coeffs,
+                                   const int64_t* coeff_offsets, uint32_t* d_out,
+                                   const int64_t* out_offsets, void* d_workspace,
+                                   size_t workspace_bytes, void* stream);
+
+/* Device time per stage of the solves of a plan made with POLYDET_STAGE_TIMING (the
+ * paper's tables report the same split: FFT, DET, IFFT, CRT). Waits for the recorded
+ * solves, writes the summed milliseconds of each stage (reduce, evaluate, determinants,
+ * interpolate, reconstruct) to ms[0..4] and the number of solves to *solves, and resets the
+ * sums. EINVAL if the plan was made without the flag. */
+polydet_status polydet_stage_times(polydet_plan_t plan, double ms[POLYDET_NUM_STAGES],
+                                   int64_t* solves);
+
+void polydet_plan_destroy(polydet_plan_t plan);
+
+const char* polydet_status_string(polydet_status status);
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char* polydet_last_error(void);
+
+/* Limits of this build: maximum n, nvars, N[v] and pn. Any pointer may be NULL. */
+void polydet_limits(int32_t* max_n, int32_t* max_vars, int32_t* max_grid_per_var,
+                    int32_t* max_primes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLYDET_H */

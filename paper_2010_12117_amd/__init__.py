@@ -1,0 +1,15 @@
+"""Exact determinants of multivariate integer-polynomial matrices on MI355X.
+
+The modular method of Wei & Chen (arXiv 2010.12117, Algorithm 1) as hand-written HIP
+kernels for gfx950 behind a C ABI (include/polydet.h); this package is the thin Python
+binding (binding.py) and the build script (build.py).
+"""
+from .binding import (DET_LANES_LOG2, FORCE_PN, HOST_ONLY, PRIME_OFFSET, STAGE_TIMING, STAGES,
+                      Plan, PolydetError,
+                      det, limbs_to_ints, limits, load_library, plan, plan_batch,
+                      solve_batch_device, solve_device)
+
+__all__ = ["DET_LANES_LOG2", "FORCE_PN", "HOST_ONLY", "PRIME_OFFSET", "STAGE_TIMING", "STAGES",
+           "Plan", "PolydetError",
+           "det", "limbs_to_ints", "limits", "load_library", "plan", "plan_batch",
+           "solve_batch_device", "solve_device"]

@@ -1,0 +1,308 @@
+"""ctypes binding of libpolydet.so (include/polydet.h), argument marshalling only.
+
+Every stage of the determinant runs in the library's HIP kernels; this module allocates
+device buffers with PyTorch, passes raw pointers and the current HIP stream, and decodes
+the two's-complement limbs into Python integers. There is no fallback: if the library is
+missing, loading fails with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpolydet.so")
+MAX_VARS = 8
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EDEVICE, ECANCELLED = range(6)
+
+
+def FORCE_PN(x: int) -> int:
+    return (x & 0xFFF) << 8
+
+
+def DET_LANES_LOG2(x: int) -> int:
+    return ((x + 1) & 0xF) << 4
+
+
+def PRIME_OFFSET(x: int) -> int:
+    return (x & 0x3FF) << 20
+
+
+HOST_ONLY = 1 << 31
+STAGE_TIMING = 1 << 30
+STAGES = ("reduce", "evaluate", "determinants", "interpolate", "reconstruct")
+
+
+class PolydetError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"polydet status {status}: {message}")
+        self.status = status
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nvars", ctypes.c_int32),
+                ("deg", ctypes.c_int32 * MAX_VARS), ("coeff_bits", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nvars", ctypes.c_int32),
+                ("deg", ctypes.c_int32 * MAX_VARS), ("D", ctypes.c_int32 * MAX_VARS),
+                ("N", ctypes.c_int32 * MAX_VARS), ("G", ctypes.c_int64),
+                ("ncoeff", ctypes.c_int64), ("nterms", ctypes.c_int64),
+                ("pn", ctypes.c_int32), ("limbs", ctypes.c_int32),
+                ("det_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("in_bytes", ctypes.c_size_t), ("out_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t), ("off_eval", ctypes.c_size_t),
+                ("off_detv", ctypes.c_size_t), ("off_coef", ctypes.c_size_t)]
+
+
+EXPORTS = ["polydet_plan", "polydet_plan_batch", "polydet_plan_query", "polydet_plan_primes",
+           "polydet_solve", "polydet_solve_batch", "polydet_plan_destroy",
+           "polydet_status_string", "polydet_last_error", "polydet_limits",
+           "polydet_stage_times"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpolydet.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2010_12117_amd.build`"
+                          " (the determinant path has no fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i32, u32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_size_t
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    lib.polydet_plan.argtypes = [ctypes.POINTER(Shape), vp, u32, ctypes.POINTER(vp)]
+    lib.polydet_plan_batch.argtypes = [ctypes.POINTER(Shape), i32, ctypes.POINTER(vp), u32,
+                                       ctypes.POINTER(vp)]
+    lib.polydet_plan_query.argtypes = [vp, i32, ctypes.POINTER(PlanInfo)]
+    lib.polydet_plan_primes.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint32), i32]
+    lib.polydet_solve.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.polydet_solve_batch.argtypes = [vp, vp, P64, vp, P64, vp, sz, vp]
+    lib.polydet_plan_destroy.argtypes = [vp]
+    lib.polydet_plan_destroy.restype = None
+    lib.polydet_status_string.argtypes = [ctypes.c_int]
+    lib.polydet_status_string.restype = ctypes.c_char_p
+    lib.polydet_last_error.argtypes = []
+    lib.polydet_last_error.restype = ctypes.c_char_p
+    lib.polydet_limits.argtypes = [ctypes.POINTER(i32)] * 4
+    lib.polydet_limits.restype = None
+    lib.polydet_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), P64]
+    for name in ["polydet_plan", "polydet_plan_batch", "polydet_plan_query",
+                 "polydet_plan_primes", "polydet_solve", "polydet_solve_batch",
+                 "polydet_stage_times"]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        lib = load_library()
+        raise PolydetError(status, lib.polydet_last_error().decode() or
+                           lib.polydet_status_string(status).decode())
+
+
+def limits():
+    lib = load_library()
+    vals = [ctypes.c_int32() for _ in range(4)]
+    lib.polydet_limits(*[ctypes.byref(v) for v in vals])
+    return dict(max_n=vals[0].value, max_vars=vals[1].value, max_grid_per_var=vals[2].value,
+                max_primes=vals[3].value)
+
+
+def make_shape(n: int, deg: Sequence[int], coeff_bits: int = 63) -> Shape:
+    s = Shape()
+    s.n = int(n)
+    s.nvars = len(deg)
+    for v, d in enumerate(deg):
+        s.deg[v] = int(d)
+    s.coeff_bits = int(coeff_bits)
+    return s
+
+
+def shape_of(arr) -> tuple:
+    """(n, deg tuple) of a coefficient array of shape (n, n, d1+1, ..., dk+1)."""
+    shp = tuple(arr.shape)
+    if len(shp) < 2 or shp[0] != shp[1]:
+        raise ValueError("coefficients must have shape (n, n, d1+1, ..., dk+1)")
+    return shp[0], tuple(x - 1 for x in shp[2:])
+
+
+def coeff_bits_of(arr: np.ndarray) -> int:
+    m = int(np.max(np.abs(arr.astype(object)))) if arr.size else 0
+    return max(0, (m - 1).bit_length()) if m > 1 else 0
+
+
+class Plan:
+    """A plan (polydet_plan / polydet_plan_batch) and its queried information."""
+
+    def __init__(self, handle, count: int):
+        self._h = handle
+        self.count = count
+        self.infos = [self._query(i) for i in range(count)]
+
+    def _query(self, i: int) -> dict:
+        lib = load_library()
+        info = PlanInfo()
+        _check(lib.polydet_plan_query(self._h, i, ctypes.byref(info)))
+        k = info.nvars
+        d = {f: getattr(info, f) for f, _ in PlanInfo._fields_}
+        for f in ("deg", "D", "N"):
+            d[f] = tuple(getattr(info, f)[v] for v in range(k))
+        arr = (ctypes.c_uint32 * max(1, info.pn))()
+        _check(lib.polydet_plan_primes(self._h, i, arr, info.pn))
+        d["primes"] = [int(arr[j]) for j in range(info.pn)]
+        return d
+
+    @property
+    def info(self) -> dict:
+        return self.infos[0]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stage_times(self) -> tuple:
+        """(dict stage -> summed ms, number of solves) since the last call; the plan must
+        have been made with STAGE_TIMING."""
+        lib = load_library()
+        ms = (ctypes.c_double * len(STAGES))()
+        n = ctypes.c_int64()
+        _check(lib.polydet_stage_times(self._h, ms, ctypes.byref(n)))
+        return {s: float(ms[i]) for i, s in enumerate(STAGES)}, int(n.value)
+
+    def close(self):
+        if self._h:
+            load_library().polydet_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan(n: int, deg: Sequence[int], host_coeffs: Optional[np.ndarray] = None,
+         coeff_bits: Optional[int] = None, flags: int = 0) -> Plan:
+    lib = load_library()
+    if coeff_bits is None:
+        coeff_bits = coeff_bits_of(host_coeffs) if host_coeffs is not None else 63
+    s = make_shape(n, deg, coeff_bits)
+    h = ctypes.c_void_p()
+    ptr = None
+    if host_coeffs is not None:
+        host_coeffs = np.ascontiguousarray(host_coeffs, dtype=np.int64)
+        ptr = host_coeffs.ctypes.data_as(ctypes.c_void_p)
+    _check(lib.polydet_plan(ctypes.byref(s), ptr, flags, ctypes.byref(h)))
+    return Plan(h, 1)
+
+
+def plan_batch(mats: Sequence[np.ndarray], use_coeffs: bool = True, flags: int = 0) -> Plan:
+    lib = load_library()
+    count = len(mats)
+    shapes = (Shape * count)()
+    ptrs = (ctypes.c_void_p * count)()
+    keep = []
+    for i, a in enumerate(mats):
+        n, deg = shape_of(a)
+        shapes[i] = make_shape(n, deg, coeff_bits_of(a))
+        if use_coeffs:
+            c = np.ascontiguousarray(a, dtype=np.int64)
+            keep.append(c)
+            ptrs[i] = c.ctypes.data
+    h = ctypes.c_void_p()
+    _check(lib.polydet_plan_batch(shapes, count, ptrs if use_coeffs else None, flags,
+                                  ctypes.byref(h)))
+    return Plan(h, count)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the determinant path runs only on the device")
+    return torch
+
+
+def _stream_ptr(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def solve_device(pl: Plan, d_coeffs, d_out=None, workspace=None, stream=None):
+    """Enqueue polydet_solve on torch device tensors (int64 coefficients). Returns
+    (out limbs as an int32 tensor of shape (ncoeff, limbs), workspace tensor)."""
+    torch = _torch()
+    info = pl.info
+    if d_coeffs.dtype != torch.int64 or not d_coeffs.is_cuda or not d_coeffs.is_contiguous():
+        raise ValueError("coefficients must be a contiguous int64 device tensor")
+    if d_coeffs.numel() * 8 != info["in_bytes"]:
+        raise ValueError("coefficient tensor size does not match the plan")
+    if d_out is None:
+        d_out = torch.empty((info["ncoeff"], info["limbs"]), dtype=torch.int32, device=d_coeffs.device)
+    if workspace is None:
+        workspace = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device=d_coeffs.device)
+    lib = load_library()
+    _check(lib.polydet_solve(pl.handle, ctypes.c_void_p(d_coeffs.data_ptr()),
+                             ctypes.c_void_p(d_out.data_ptr()),
+                             ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                             _stream_ptr(torch, stream)))
+    return d_out, workspace
+
+
+def solve_batch_device(pl: Plan, d_coeffs, coeff_offsets: Sequence[int], d_out,
+                       out_offsets: Sequence[int], workspace=None, stream=None):
+    torch = _torch()
+    lib = load_library()
+    if workspace is None:
+        workspace = torch.empty(pl.infos[0]["workspace_bytes"], dtype=torch.uint8,
+                                device=d_coeffs.device)
+    co = np.ascontiguousarray(coeff_offsets, dtype=np.int64)
+    oo = np.ascontiguousarray(out_offsets, dtype=np.int64)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    _check(lib.polydet_solve_batch(pl.handle, ctypes.c_void_p(d_coeffs.data_ptr()),
+                                   co.ctypes.data_as(P64), ctypes.c_void_p(d_out.data_ptr()),
+                                   oo.ctypes.data_as(P64), ctypes.c_void_p(workspace.data_ptr()),
+                                   workspace.numel(), _stream_ptr(torch, stream)))
+    return workspace
+
+
+def limbs_to_ints(limbs: np.ndarray) -> List[int]:
+    """Rows of little-endian two's-complement uint32 limbs -> Python ints."""
+    limbs = np.asarray(limbs).view(np.uint32).astype(object)
+    L = limbs.shape[-1]
+    out = []
+    for row in limbs.reshape(-1, L):
+        x = 0
+        for l in range(L - 1, -1, -1):
+            x = (x << 32) | int(row[l])
+        if x >> (32 * L - 1):
+            x -= 1 << (32 * L)
+        out.append(x)
+    return out
+
+
+def det(coeffs: np.ndarray, device: str = "cuda", flags: int = 0) -> np.ndarray:
+    """Exact determinant of one polynomial matrix. `coeffs` is int64 of shape
+    (n, n, d1+1, ..., dk+1); returns an object array of shape (D1+1, ..., Dk+1)."""
+    torch = _torch()
+    coeffs = np.ascontiguousarray(coeffs, dtype=np.int64)
+    n, deg = shape_of(coeffs)
+    pl = plan(n, deg, host_coeffs=coeffs, flags=flags)
+    d_coeffs = torch.from_numpy(coeffs).to(device)
+    out, _ = solve_device(pl, d_coeffs)
+    torch.cuda.synchronize()
+    vals = limbs_to_ints(out.cpu().numpy())
+    box = tuple(d + 1 for d in pl.info["D"])
+    res = np.empty(len(vals), dtype=object)
+    for i, v in enumerate(vals):
+        res[i] = v
+    return res.reshape(box) if box else res.reshape(())

@@ -1,0 +1,20 @@
+// Stage launchers of one solve (all asynchronous on the given stream). The workspace
+// layout and the device tables come from the plan (plan.h).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "plan.h"
+
+namespace pd {
+
+// Whether an elimination kernel is compiled for this order and lanes-per-matrix.
+bool det_config_supported(int n, int lanes);
+
+hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st);
+hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st);
+hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st);
+hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st);
+hipError_t run_reconstruct(const MatPlan& P, uint8_t* ws, uint32_t* out, hipStream_t st);
+
+}  // namespace pd

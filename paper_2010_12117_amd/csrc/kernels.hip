@@ -1,0 +1,397 @@
+// HIP kernels for gfx950 of the modular determinant (Wei & Chen, arXiv 2010.12117,
+// Algorithm 1): reduction of the integer coefficients, evaluation on the grid of roots of
+// unity (the FFT stage), one determinant per (prime, grid point) (the DET stage),
+// interpolation (the IFFT stage) and mixed-radix reconstruction (the CRT stage).
+//
+// Every value below is a Montgomery representative (modarith.h) until the reconstruction.
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "det.h"
+#include "kernels.h"
+#include "modarith.h"
+
+namespace pd {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned blocks_for(int64_t work, int per_block = kBlock) {
+  int64_t b = (work + per_block - 1) / per_block;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ------------------------------------------------------------------------------------
+// S1: int64 coefficient -> representative of (c mod p) for every prime.
+// |c| = hi 2^32 + lo with hi <= 2^31, so c~ = mm(hi, R^3) + mm(lo, R^2), negated for c < 0.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void reduce_kernel(const int64_t* __restrict__ in,
+                                                        uint32_t* __restrict__ out,
+                                                        int64_t count, int pn,
+                                                        const PrimeConst* __restrict__ pcs) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= count) return;
+  const int64_t c = in[i];
+  const bool neg = c < 0;
+  const uint64_t a = neg ? (uint64_t)(-(c + 1)) + 1u : (uint64_t)c;
+  const uint32_t hi = (uint32_t)(a >> 32), lo = (uint32_t)a;
+  for (int q = 0; q < pn; ++q) {
+    const PrimeConst P = pcs[q];
+    uint32_t r = addm(mm(hi, P.r3, P.p, P.pinv), mm(lo, P.r2, P.p, P.pinv), P.p);
+    if (neg) r = negm(r, P.p);
+    out[(int64_t)q * count + i] = r;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// S2: evaluation along one variable. For every line (b, o, q) of
+//   in  [B][outer][m][inner]   (coefficients of x_v^e, e < m, other axes as given)
+//   out [B][outer][Nv][inner]  out[j] = sum_e in[e] w_v^{e j}
+// the values at the Nv-th roots of unity (the DFT over Z/pZ of Section 2, restricted to the
+// m nonzero leading coefficients of the zero-padded line). b = prime * nent + entry.
+// Consecutive lanes take consecutive q, so loads and stores are coalesced whenever
+// inner >= 64; the twiddles for a given j are then the same address across the wave.
+// ------------------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void expand_kernel(
+    const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t B, int64_t outer,
+    int m, int Nv, int64_t inner, int64_t nent, const uint32_t* __restrict__ tw,
+    int64_t tw_stride, const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= B * outer * inner) return;
+  const int64_t q = idx % inner;
+  const int64_t bo = idx / inner;
+  const int64_t b = bo / outer;
+  const int prime = (int)(b / nent);
+  const int64_t entry = b - (int64_t)prime * nent;
+  uint32_t* dst = out + bo * Nv * inner + q;
+  if (zero && zero[entry]) {
+    for (int j = 0; j < Nv; ++j) dst[(int64_t)j * inner] = 0u;
+    return;
+  }
+  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv;
+  const uint32_t* src = in + bo * m * inner + q;
+  const uint32_t* w = tw + (int64_t)prime * tw_stride;
+  uint32_t x[M];
+#pragma unroll
+  for (int e = 0; e < M; ++e) x[e] = e < m ? src[(int64_t)e * inner] : 0u;
+  const int mask = Nv - 1;
+  for (int j = 0; j < Nv; ++j) {
+    uint32_t acc = x[0];
+#pragma unroll
+    for (int e = 1; e < M; e += 2) {
+      if (e + 1 < M) {
+        acc = addm(acc,
+                   mm2(x[e], w[(e * j) & mask], x[e + 1], w[((e + 1) * j) & mask], p, pinv), p);
+      } else {
+        acc = addm(acc, mm(x[e], w[(e * j) & mask], p, pinv), p);
+      }
+    }
+    dst[(int64_t)j * inner] = acc;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// S4: interpolation along one variable (inverse DFT: opposite sign in the exponent; the
+// 1/N factor is applied once in the reconstruction). A block loads a tile of W lines of
+// length Nv into LDS in bit-reversed order, runs log2 Nv radix-2 decimation-in-time stages
+// and writes the first D_v + 1 outputs of each line:
+//   in  [pn][outer][Nv][inner] -> out [pn][outer][Dv+1][inner].
+// ------------------------------------------------------------------------------------
+constexpr int kTileElems = 8192;  // 32 KB of LDS
+
+__global__ __launch_bounds__(kBlock) void intt_kernel(
+    const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int pn, int64_t outer,
+    int Nv, int logN, int64_t inner, int Dv1, int W, const uint32_t* __restrict__ itw,
+    int64_t tw_stride, const PrimeConst* __restrict__ pcs) {
+  __shared__ uint32_t tile[kTileElems];
+  const int64_t lines = outer * inner;
+  const int64_t tiles_per_prime = (lines + W - 1) / W;
+  const int prime = (int)(blockIdx.x / tiles_per_prime);
+  const int64_t line0 = (blockIdx.x - (int64_t)prime * tiles_per_prime) * W;
+  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv;
+  const uint32_t* w = itw + (int64_t)prime * tw_stride;
+  const uint32_t* src = in + (int64_t)prime * outer * Nv * inner;
+  uint32_t* dst = out + (int64_t)prime * outer * Dv1 * inner;
+  const int nW = (int)((lines - line0) < W ? (lines - line0) : W);
+  const int total = Nv * W;
+  // load: element j of local line l goes to tile[brev(j) * W + l]
+  for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+    int j, l;
+    if (inner >= W) { j = idx / W; l = idx % W; } else { l = idx / Nv; j = idx % Nv; }
+    uint32_t v = 0u;
+    if (l < nW) {
+      const int64_t line = line0 + l;
+      const int64_t o = line / inner, q = line % inner;
+      v = src[(o * Nv + j) * inner + q];
+    }
+    const int rj = logN ? (int)(__brev((unsigned)j) >> (32 - logN)) : 0;
+    tile[rj * W + l] = v;
+  }
+  __syncthreads();
+  for (int s = 1; s <= logN; ++s) {
+    const int half = 1 << (s - 1);
+    const int stride = Nv >> s;  // twiddle index step: w^{pos * N / 2^s}
+    for (int bi = threadIdx.x; bi < (Nv / 2) * W; bi += kBlock) {
+      const int l = bi % W;
+      const int b = bi / W;
+      const int grp = b / half, pos = b % half;
+      const int i0 = grp * 2 * half + pos, i1 = i0 + half;
+      const uint32_t u = tile[i0 * W + l];
+      const uint32_t v = mm(tile[i1 * W + l], w[pos * stride], p, pinv);
+      tile[i0 * W + l] = addm(u, v, p);
+      tile[i1 * W + l] = subm(u, v, p);
+    }
+    __syncthreads();
+  }
+  const int otot = Dv1 * W;
+  for (int idx = threadIdx.x; idx < otot; idx += kBlock) {
+    int e, l;
+    if (inner >= W) { e = idx / W; l = idx % W; } else { l = idx / Dv1; e = idx % Dv1; }
+    if (l < nW) {
+      const int64_t line = line0 + l;
+      const int64_t o = line / inner, q = line % inner;
+      dst[(o * Dv1 + e) * inner + q] = tile[e * W + l];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// S5: mixed-radix conversion (Section 3.4, Algorithm 4; one lane per coefficient, as the
+// paper parallelises over coefficients rather than digits). With x_i the residue mod p_i:
+//   alpha_0 = x_0,  alpha_i = (x_i - sum_{j<i} alpha_j (p_0..p_{j-1} mod p_i)) c_i mod p_i,
+//   c_i = (p_0..p_{i-1})^{-1} mod p_i,  X = sum_i alpha_i p_0..p_{i-1} (Horner, top down),
+// then the symmetric range: X - M when X > (M-1)/2, written as L two's-complement limbs.
+// ------------------------------------------------------------------------------------
+template <int PN>
+__global__ __launch_bounds__(kBlock) void garner_kernel(
+    const uint32_t* __restrict__ coef, uint32_t* __restrict__ out, int64_t C, int pn, int L,
+    const PrimeConst* __restrict__ pcs, const uint32_t* __restrict__ gw,
+    const uint32_t* __restrict__ gc, const uint32_t* __restrict__ mlimbs,
+    const uint32_t* __restrict__ hlimbs) {
+  __shared__ uint32_t s_gw[PN * PN];
+  __shared__ uint32_t s_p[PN], s_pinv[PN], s_gc[PN], s_scale[PN], s_m[PN], s_h[PN];
+  for (int i = threadIdx.x; i < pn * pn; i += kBlock) s_gw[(i / pn) * PN + i % pn] = gw[i];
+  for (int i = threadIdx.x; i < pn; i += kBlock) {
+    s_p[i] = pcs[i].p;
+    s_pinv[i] = pcs[i].pinv;
+    s_gc[i] = gc[i];
+    s_scale[i] = pcs[i].scale;
+  }
+  for (int i = threadIdx.x; i < L; i += kBlock) {
+    s_m[i] = mlimbs[i];
+    s_h[i] = hlimbs[i];
+  }
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= C) return;
+  uint32_t alpha[PN];
+#pragma unroll
+  for (int i = 0; i < PN; ++i) {
+    if (i < pn) {
+      const uint32_t p = s_p[i], pinv = s_pinv[i];
+      // residue out of Montgomery form and divided by G (the inverse-DFT factor)
+      const uint32_t x = mm(coef[(int64_t)i * C + c], s_scale[i], p, pinv);
+      uint32_t acc = 0u;
+#pragma unroll
+      for (int j = 0; j < PN; ++j) {
+        if (j < i) acc = addm(acc, mm(alpha[j], s_gw[i * PN + j], p, pinv), p);
+      }
+      alpha[i] = mm(subm(x, acc, p), s_gc[i], p, pinv);
+    } else {
+      alpha[i] = 0u;
+    }
+  }
+  // Horner: X = alpha_{pn-1}; X = X p_i + alpha_i for i = pn-2 .. 0
+  uint32_t X[PN];
+#pragma unroll
+  for (int l = 0; l < PN; ++l) X[l] = 0u;
+#pragma unroll
+  for (int i = PN - 1; i >= 0; --i) {
+    if (i < pn) {
+      const uint32_t pi = (i == pn - 1) ? 0u : s_p[i];
+      uint64_t carry = alpha[i];
+#pragma unroll
+      for (int l = 0; l < PN; ++l) {
+        const uint64_t tt = (uint64_t)X[l] * pi + carry;
+        X[l] = (uint32_t)tt;
+        carry = tt >> 32;
+      }
+    }
+  }
+  // X > (M-1)/2 ?  compare from the top limb
+  int cmp = 0;
+#pragma unroll
+  for (int l = PN - 1; l >= 0; --l) {
+    if (l < L && cmp == 0) cmp = (X[l] > s_h[l]) ? 1 : (X[l] < s_h[l] ? -1 : 0);
+  }
+  if (cmp > 0) {
+    uint32_t borrow = 0u;
+#pragma unroll
+    for (int l = 0; l < PN; ++l) {
+      if (l < L) {
+        const uint64_t d = (uint64_t)X[l] - s_m[l] - borrow;
+        X[l] = (uint32_t)d;
+        borrow = (uint32_t)(d >> 63);
+      }
+    }
+  }
+  uint32_t* o = out + c * L;
+#pragma unroll
+  for (int l = 0; l < PN; ++l) {
+    if (l < L) o[l] = X[l];
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// launch helpers
+// ------------------------------------------------------------------------------------
+template <int M>
+hipError_t launch_expand_m(const MatPlan& P, const uint32_t* in, uint32_t* out, int64_t outer,
+                           int v, int64_t inner, hipStream_t st) {
+  const int64_t B = (int64_t)P.pn * P.nent;
+  const int64_t work = B * outer * inner;
+  hipLaunchKernelGGL(expand_kernel<M>, dim3(blocks_for(work)), dim3(kBlock), 0, st, in, out, B,
+                     outer, P.m[v], P.N[v], inner, P.nent, P.d_tw + P.tw_off[v], P.tw_stride,
+                     P.d_pc, P.d_zero);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const MatPlan& P, const uint32_t* in, uint32_t* out, int64_t outer,
+                         int v, int64_t inner, hipStream_t st) {
+  const int m = P.m[v];
+  switch (m) {
+    case 1: return launch_expand_m<1>(P, in, out, outer, v, inner, st);
+    case 2: return launch_expand_m<2>(P, in, out, outer, v, inner, st);
+    case 3: return launch_expand_m<3>(P, in, out, outer, v, inner, st);
+    case 4: return launch_expand_m<4>(P, in, out, outer, v, inner, st);
+    case 5: return launch_expand_m<5>(P, in, out, outer, v, inner, st);
+    case 6: return launch_expand_m<6>(P, in, out, outer, v, inner, st);
+    case 7: return launch_expand_m<7>(P, in, out, outer, v, inner, st);
+    case 8: return launch_expand_m<8>(P, in, out, outer, v, inner, st);
+    default:
+      if (m <= 16) return launch_expand_m<16>(P, in, out, outer, v, inner, st);
+      return launch_expand_m<32>(P, in, out, outer, v, inner, st);
+  }
+}
+
+template <int N>
+hipError_t launch_det_n(const MatPlan& P, const uint32_t* eval, uint32_t* detv, hipStream_t st) {
+  switch (P.det_lanes) {
+    case 1:
+      if constexpr (N <= 12) return det_launch<N, 1>(eval, detv, P.G, P.pn, P.d_pc, st);
+      break;
+    case 2:
+      if constexpr (N >= 2 && N <= 16) return det_launch<N, 2>(eval, detv, P.G, P.pn, P.d_pc, st);
+      break;
+    case 4:
+      if constexpr (N >= 4 && N <= 24) return det_launch<N, 4>(eval, detv, P.G, P.pn, P.d_pc, st);
+      break;
+    case 8:
+      if constexpr (N >= 8) return det_launch<N, 8>(eval, detv, P.G, P.pn, P.d_pc, st);
+      break;
+    case 16:
+      if constexpr (N >= 16) return det_launch<N, 16>(eval, detv, P.G, P.pn, P.d_pc, st);
+      break;
+    default:
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int... Ns>
+hipError_t dispatch_det(std::integer_sequence<int, Ns...>, const MatPlan& P, const uint32_t* eval,
+                        uint32_t* detv, hipStream_t st) {
+  hipError_t r = hipErrorInvalidValue;
+  ((P.n == Ns + 1 ? (r = launch_det_n<Ns + 1>(P, eval, detv, st), 0) : 0), ...);
+  return r;
+}
+
+template <int PN>
+hipError_t launch_garner_pn(const MatPlan& P, const uint32_t* coef, uint32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(garner_kernel<PN>, dim3(blocks_for(P.C)), dim3(kBlock), 0, st, coef, out, P.C,
+                     P.pn, P.L, P.d_pc, P.d_gw, P.d_gc, P.d_mlimbs, P.d_hlimbs);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool det_config_supported(int n, int lanes) {
+  if (n < 1 || n > kMaxN) return false;
+  switch (lanes) {
+    case 1: return n <= 12;
+    case 2: return n >= 2 && n <= 16;
+    case 4: return n >= 4 && n <= 24;
+    case 8: return n >= 8;
+    case 16: return n >= 16;
+    default: return false;
+  }
+}
+
+hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st) {
+  const int64_t count = P.nent * P.T;
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(count)), dim3(kBlock), 0, st, coeffs,
+                     (uint32_t*)(ws + P.off_res), count, P.pn, P.d_pc);
+  return hipGetLastError();
+}
+
+hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
+  if (P.k == 0) return hipSuccess;  // the residues are the values at the single point
+  const uint32_t* in = (const uint32_t*)(ws + P.off_res);
+  uint32_t* bufs[2] = {(uint32_t*)(ws + P.off_tmpA), (uint32_t*)(ws + P.off_tmpB)};
+  int which = 0;
+  for (int v = P.k - 1; v >= 0; --v) {
+    int64_t outer = 1, inner = 1;
+    for (int u = 0; u < v; ++u) outer *= P.m[u];
+    for (int u = v + 1; u < P.k; ++u) inner *= P.N[u];
+    uint32_t* out = v == 0 ? (uint32_t*)(ws + P.off_eval) : bufs[which];
+    hipError_t err = launch_expand(P, in, out, outer, v, inner, st);
+    if (err != hipSuccess) return err;
+    in = out;
+    which ^= 1;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st) {
+  return dispatch_det(std::make_integer_sequence<int, kMaxN>{}, P,
+                      (const uint32_t*)(ws + P.off_eval), (uint32_t*)(ws + P.off_detv), st);
+}
+
+hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
+  if (P.k == 0) return hipSuccess;
+  const uint32_t* in = (const uint32_t*)(ws + P.off_detv);
+  uint32_t* bufs[2] = {(uint32_t*)(ws + P.off_iA), (uint32_t*)(ws + P.off_iB)};
+  int which = 0;
+  for (int v = 0; v < P.k; ++v) {
+    int64_t outer = 1, inner = 1;
+    for (int u = 0; u < v; ++u) outer *= P.D[u] + 1;
+    for (int u = v + 1; u < P.k; ++u) inner *= P.N[u];
+    uint32_t* out = v == P.k - 1 ? (uint32_t*)(ws + P.off_coef) : bufs[which];
+    const int Nv = P.N[v];
+    int logN = 0;
+    while ((1 << logN) < Nv) ++logN;
+    const int W = kTileElems / Nv;
+    const int64_t lines = outer * inner;
+    const int64_t tiles = (lines + W - 1) / W;
+    hipLaunchKernelGGL(intt_kernel, dim3((unsigned)(tiles * P.pn)), dim3(kBlock), 0, st, in, out,
+                       P.pn, outer, Nv, logN, inner, P.D[v] + 1, W, P.d_itw + P.tw_off[v],
+                       P.tw_stride, P.d_pc);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    in = out;
+    which ^= 1;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_reconstruct(const MatPlan& P, uint8_t* ws, uint32_t* out, hipStream_t st) {
+  const uint32_t* coef = (const uint32_t*)(ws + P.off_coef);
+  if (P.pn <= 8) return launch_garner_pn<8>(P, coef, out, st);
+  if (P.pn <= 16) return launch_garner_pn<16>(P, coef, out, st);
+  return launch_garner_pn<32>(P, coef, out, st);
+}
+
+}  // namespace pd

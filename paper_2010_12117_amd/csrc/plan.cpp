@@ -1,0 +1,399 @@
+// Host-side plan: see plan.h.
+#include "plan.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace pd {
+
+namespace {
+
+uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) {
+  return (uint64_t)((unsigned __int128)a * b % m);
+}
+
+// Deterministic Miller-Rabin for 32-bit integers (bases 2, 7, 61 cover all n < 4.7e9).
+bool is_prime_u32(uint32_t n) {
+  if (n < 2) return false;
+  for (uint32_t q : {2u, 3u, 5u, 7u, 11u, 13u}) {
+    if (n % q == 0) return n == q;
+  }
+  uint32_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) { d >>= 1; ++s; }
+  for (uint32_t a : {2u, 7u, 61u}) {
+    if (a % n == 0) continue;
+    uint64_t x = powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s; ++r) {
+      x = mulmod64(x, x, n);
+      if (x == n - 1) { comp = false; break; }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+int64_t next_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Little-endian multi-limb helpers for M = prod p_i.
+void big_mul_small(std::vector<uint32_t>& a, uint32_t b) {
+  uint64_t carry = 0;
+  for (auto& x : a) {
+    uint64_t t = (uint64_t)x * b + carry;
+    x = (uint32_t)t;
+    carry = t >> 32;
+  }
+  if (carry) a.push_back((uint32_t)carry);
+}
+
+int big_bitlen(const std::vector<uint32_t>& a) {
+  for (int i = (int)a.size() - 1; i >= 0; --i) {
+    if (a[i]) return 32 * i + 32 - __builtin_clz(a[i]);
+  }
+  return 0;
+}
+
+}  // namespace
+
+uint32_t powmod(uint32_t b, uint64_t e, uint32_t p) {
+  uint64_t r = 1 % p, x = b % p;
+  while (e) {
+    if (e & 1) r = mulmod64(r, x, p);
+    x = mulmod64(x, x, p);
+    e >>= 1;
+  }
+  return (uint32_t)r;
+}
+
+const std::vector<uint32_t>& prime_table() {
+  static const std::vector<uint32_t> table = [] {
+    std::vector<uint32_t> t;
+    const uint64_t step = 1ull << 16;
+    for (uint64_t c = ((1ull << 31) - 1) / step; c * step + 1 > (1ull << 30); --c) {
+      const uint64_t p = c * step + 1;
+      if (p < (1ull << 31) && is_prime_u32((uint32_t)p)) t.push_back((uint32_t)p);
+    }
+    return t;
+  }();
+  return table;
+}
+
+uint32_t primitive_root(uint32_t p) {
+  // p - 1 = c * 2^16: its prime factors are 2 and those of c.
+  std::vector<uint32_t> qs;
+  uint32_t m = p - 1;
+  for (uint32_t f = 2; (uint64_t)f * f <= m; ++f) {
+    if (m % f == 0) {
+      qs.push_back(f);
+      while (m % f == 0) m /= f;
+    }
+  }
+  if (m > 1) qs.push_back(m);
+  for (uint32_t g = 2;; ++g) {
+    bool ok = true;
+    for (uint32_t q : qs) {
+      if (powmod(g, (p - 1) / q, p) == 1) { ok = false; break; }
+    }
+    if (ok) return g;
+  }
+}
+
+static int default_det_lanes(int n) {
+  if (n <= 12) return 1;
+  if (n <= 16) return 2;
+  if (n <= 24) return 4;
+  return 8;
+}
+
+std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t flags,
+                          MatPlan* out, bool* unsupported) {
+  *unsupported = false;
+  MatPlan P;
+  if (s.n < 1) return "matrix order n must be >= 1";
+  if (s.k < 0 || s.k > kMaxVars) return "nvars must be in 0..8";
+  if (s.coeff_bits < 0 || s.coeff_bits > 63) return "coeff_bits must be in 0..63";
+  for (int v = 0; v < s.k; ++v) {
+    if (s.deg[v] < 0) return "degrees must be >= 0";
+  }
+  if (s.n > kMaxN) {
+    *unsupported = true;
+    return "matrix order above " + std::to_string(kMaxN) + " is not supported";
+  }
+  P.n = s.n;
+  P.k = s.k;
+  P.nent = (int64_t)s.n * s.n;
+  P.G = P.C = P.T = 1;
+  for (int v = 0; v < s.k; ++v) {
+    if (s.deg[v] > kMaxEntryDeg) {
+      *unsupported = true;
+      return "entry degree above " + std::to_string(kMaxEntryDeg) + " is not supported";
+    }
+    P.deg[v] = s.deg[v];
+    P.m[v] = s.deg[v] + 1;
+    P.D[v] = s.n * s.deg[v];
+    const int64_t Nv = next_pow2((int64_t)P.D[v] + 1);
+    if (Nv > kMaxGrid) {
+      *unsupported = true;
+      return "grid size per variable above " + std::to_string(kMaxGrid) + " is not supported";
+    }
+    P.N[v] = (int)Nv;
+    P.G *= Nv;
+    P.C *= P.D[v] + 1;
+    P.T *= P.m[v];
+  }
+
+  // Bound on the squared coefficients of det M (Hadamard on 1-norms), as log2 with a
+  // margin that covers the rounding of the long-double sums many times over.
+  long double log2b = 0;
+  bool zero_bound = false;
+  if (host_coeffs) {
+    P.entry_zero.assign(P.nent, 0);
+    std::vector<long double> norm(P.nent);
+    for (int64_t e = 0; e < P.nent; ++e) {
+      long double acc = 0;
+      bool nz = false;
+      const int64_t* c = host_coeffs + e * P.T;
+      for (int64_t t = 0; t < P.T; ++t) {
+        if (c[t]) {
+          nz = true;
+          acc += fabsl((long double)c[t]);
+        }
+      }
+      norm[e] = acc;
+      P.entry_zero[e] = nz ? 0 : 1;
+    }
+    long double rows = 0, cols = 0;
+    bool rz = false, cz = false;
+    for (int i = 0; i < s.n; ++i) {
+      long double sr = 0, sc = 0;
+      for (int j = 0; j < s.n; ++j) {
+        sr += norm[i * s.n + j] * norm[i * s.n + j];
+        sc += norm[j * s.n + i] * norm[j * s.n + i];
+      }
+      if (sr == 0) rz = true; else rows += log2l(sr);
+      if (sc == 0) cz = true; else cols += log2l(sc);
+    }
+    if (rz || cz) zero_bound = true;
+    log2b = std::min(rows, cols);
+  } else {
+    // every |c| <= 2^coeff_bits: |a_ij|_1 <= T 2^cb, so B^2 <= (n T^2 4^cb)^n
+    log2b = (long double)s.n * (log2l((long double)s.n) + 2 * log2l((long double)P.T) +
+                                2.0L * s.coeff_bits);
+  }
+  log2b += 1e-6L * (fabsl(log2b) + 1) + 1.0L;  // safety margin (may add one prime)
+  P.log2_bound_sq = (double)log2b;
+
+  const auto& table = prime_table();
+  const int force_pn = (int)((flags >> 8) & 0xFFF);
+  P.prime_off = (int)((flags >> 20) & 0x3FF);
+  // least pn with sum log2 p_i > 1 + log2(B^2) / 2, i.e. M^2 > 4 B^2
+  int need = 1;
+  if (!zero_bound) {
+    long double acc = 0;
+    const long double target = 1.0L + log2b / 2;
+    need = 0;
+    while (acc <= target) {
+      if (P.prime_off + need >= (int)table.size()) {
+        *unsupported = true;
+        return "the coefficient bound needs more primes than the table holds";
+      }
+      acc += log2l((long double)table[P.prime_off + need]) - 1e-12L;
+      ++need;
+    }
+    need = std::max(need, 1);
+  }
+  if (force_pn) {
+    if (force_pn < need) return "forced prime count is below what the bound needs";
+    need = force_pn;
+  }
+  if (need > kMaxPrimes) {
+    *unsupported = true;
+    return "more than " + std::to_string(kMaxPrimes) + " primes are not supported";
+  }
+  if (P.prime_off + need > (int)table.size()) {
+    *unsupported = true;
+    return "prime offset and count exceed the prime table";
+  }
+  P.pn = need;
+  P.primes.assign(table.begin() + P.prime_off, table.begin() + P.prime_off + need);
+
+  std::vector<uint32_t> Mb{1};
+  for (uint32_t p : P.primes) big_mul_small(Mb, p);
+  P.L = std::max(1, (big_bitlen(Mb) + 31) / 32);
+
+  P.pc.resize(P.pn);
+  for (int i = 0; i < P.pn; ++i) {
+    const uint32_t p = P.primes[i];
+    uint32_t inv = p;  // Newton iteration for p^{-1} mod 2^32
+    for (int it = 0; it < 5; ++it) inv *= 2u - p * inv;
+    PrimeConst c{};
+    c.p = p;
+    c.pinv = 0u - inv;
+    c.r1 = (uint32_t)((1ull << 32) % p);
+    c.r2 = (uint32_t)mulmod64(c.r1, c.r1, p);
+    c.r3 = (uint32_t)mulmod64(c.r2, c.r1, p);
+    c.scale = powmod((uint32_t)(P.G % p), p - 2, p);
+    P.pc[i] = c;
+  }
+
+  P.det_lanes = default_det_lanes(P.n);
+  const int dl = (int)((flags >> 4) & 0xF);
+  if (dl) {
+    const int want = 1 << (dl - 1);
+    if (want > 16) return "elimination lanes must be 1..16";
+    P.det_lanes = want;
+  }
+
+  // workspace layout
+  const size_t pn = P.pn;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  P.off_res = take(pn * P.nent * P.T * 4);
+  // forward passes run over the last variable first; the output of pass v has shape
+  // [pn*nent][prod_{u<v} m_u][prod_{u>=v} N_u]
+  size_t inter = 0;
+  for (int v = s.k - 1; v >= 1; --v) {
+    int64_t sz = 1;
+    for (int u = 0; u < v; ++u) sz *= P.m[u];
+    for (int u = v; u < s.k; ++u) sz *= P.N[u];
+    inter = std::max(inter, (size_t)sz);
+  }
+  P.off_tmpA = take(pn * P.nent * inter * 4);
+  P.off_tmpB = take(pn * P.nent * inter * 4);
+  P.off_eval = s.k == 0 ? P.off_res : take(pn * P.nent * P.G * 4);
+  P.off_detv = take(pn * P.G * 4);
+  // interpolation passes run over the first variable first, trimming N_v to D_v + 1
+  size_t iinter = 0;
+  for (int v = 0; v + 1 < s.k; ++v) {
+    int64_t sz = 1;
+    for (int u = 0; u <= v; ++u) sz *= P.D[u] + 1;
+    for (int u = v + 1; u < s.k; ++u) sz *= P.N[u];
+    iinter = std::max(iinter, (size_t)sz);
+  }
+  P.off_iA = take(pn * iinter * 4);
+  P.off_iB = take(pn * iinter * 4);
+  P.off_coef = s.k == 0 ? P.off_detv : take(pn * P.C * 4);
+  P.ws_bytes = std::max<size_t>(off, 256);
+  P.in_bytes = (size_t)P.nent * P.T * 8;
+  P.out_bytes = (size_t)P.C * P.L * 4;
+  *out = std::move(P);
+  return "";
+}
+
+int upload_tables(Plan* plan) {
+  // layout per matrix: pc | tw | itw | gw | gc | mlimbs | hlimbs | zero
+  std::vector<size_t> offs;
+  size_t total = 0;
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  struct Sizes { size_t pc, tw, gw, gc, ml, zero; };
+  std::vector<Sizes> sz;
+  for (auto& P : plan->mats) {
+    int64_t stride = 0;
+    for (int v = 0; v < P.k; ++v) {
+      P.tw_off[v] = stride;
+      stride += P.N[v];
+    }
+    P.tw_stride = std::max<int64_t>(stride, 1);
+    Sizes z;
+    z.pc = al(sizeof(PrimeConst) * P.pn);
+    z.tw = al(4 * P.pn * P.tw_stride);
+    z.gw = al(4 * P.pn * P.pn);
+    z.gc = al(4 * P.pn);
+    z.ml = al(4 * P.L);
+    z.zero = P.entry_zero.empty() ? 0 : al(P.nent);
+    sz.push_back(z);
+    offs.push_back(total);
+    total += z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero;
+  }
+  std::vector<uint8_t> host(std::max<size_t>(total, 256), 0);
+  for (size_t idx = 0; idx < plan->mats.size(); ++idx) {
+    MatPlan& P = plan->mats[idx];
+    const Sizes& z = sz[idx];
+    uint8_t* base = host.data() + offs[idx];
+    std::memcpy(base, P.pc.data(), sizeof(PrimeConst) * P.pn);
+    uint32_t* tw = (uint32_t*)(base + z.pc);
+    uint32_t* itw = (uint32_t*)(base + z.pc + z.tw);
+    for (int i = 0; i < P.pn; ++i) {
+      const uint32_t p = P.primes[i];
+      const uint32_t g = primitive_root(p);
+      for (int v = 0; v < P.k; ++v) {
+        const uint32_t w = powmod(g, (p - 1) / (uint32_t)P.N[v], p);
+        const uint32_t wi = powmod(w, p - 2, p);
+        uint64_t a = P.pc[i].r1, b = P.pc[i].r1;  // Montgomery representatives of w^t
+        for (int t = 0; t < P.N[v]; ++t) {
+          tw[i * P.tw_stride + P.tw_off[v] + t] = (uint32_t)a;
+          itw[i * P.tw_stride + P.tw_off[v] + t] = (uint32_t)b;
+          a = mulmod64(a, w, p);
+          b = mulmod64(b, wi, p);
+        }
+      }
+    }
+    uint32_t* gw = (uint32_t*)(base + z.pc + 2 * z.tw);
+    uint32_t* gc = (uint32_t*)(base + z.pc + 2 * z.tw + z.gw);
+    for (int i = 0; i < P.pn; ++i) {
+      const uint32_t pi = P.primes[i];
+      uint64_t mj = 1;  // (p_0 .. p_{j-1}) mod p_i
+      for (int j = 0; j < P.pn; ++j) {
+        gw[i * P.pn + j] = j < i ? (uint32_t)mulmod64(mj, P.pc[i].r1, pi) : 0u;
+        if (j < i) mj = mulmod64(mj, P.primes[j] % pi, pi);
+      }
+      // here mj = (p_0 .. p_{i-1}) mod p_i
+      const uint32_t ci = i == 0 ? 1u : powmod((uint32_t)mj, pi - 2, pi);
+      gc[i] = (uint32_t)mulmod64(ci, P.pc[i].r1, pi);
+    }
+    std::vector<uint32_t> Mb{1};
+    for (uint32_t p : P.primes) big_mul_small(Mb, p);
+    Mb.resize(P.L, 0);
+    std::vector<uint32_t> Hb(P.L, 0);  // (M - 1) / 2 = M >> 1 since M is odd
+    for (int l = 0; l < P.L; ++l) {
+      Hb[l] = (Mb[l] >> 1) | (l + 1 < P.L ? (Mb[l + 1] << 31) : 0u);
+    }
+    uint32_t* ml = (uint32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc);
+    uint32_t* hl = (uint32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + z.ml);
+    std::memcpy(ml, Mb.data(), 4 * P.L);
+    std::memcpy(hl, Hb.data(), 4 * P.L);
+    if (z.zero) {
+      std::memcpy(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml, P.entry_zero.data(), P.nent);
+    }
+  }
+  void* d = nullptr;
+  hipError_t err = hipMalloc(&d, host.size());
+  if (err != hipSuccess) return (int)err;
+  err = hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (err != hipSuccess) {
+    (void)hipFree(d);
+    return (int)err;
+  }
+  plan->d_tables = d;
+  for (size_t idx = 0; idx < plan->mats.size(); ++idx) {
+    MatPlan& P = plan->mats[idx];
+    const Sizes& z = sz[idx];
+    uint8_t* base = (uint8_t*)d + offs[idx];
+    P.d_pc = (const PrimeConst*)base;
+    P.d_tw = (const uint32_t*)(base + z.pc);
+    P.d_itw = (const uint32_t*)(base + z.pc + z.tw);
+    P.d_gw = (const uint32_t*)(base + z.pc + 2 * z.tw);
+    P.d_gc = (const uint32_t*)(base + z.pc + 2 * z.tw + z.gw);
+    P.d_mlimbs = (const uint32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc);
+    P.d_hlimbs = (const uint32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + z.ml);
+    P.d_zero = z.zero ? (const uint8_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml) : nullptr;
+  }
+  return 0;
+}
+
+}  // namespace pd

@@ -1,0 +1,79 @@
+// Host-side plan of the modular determinant (Algorithm 1 of Wei & Chen, arXiv 2010.12117):
+// degree bound and power-of-two grid, coefficient bound and prime count (Section 2, after
+// Algorithm 1, and equation "primes"), per-prime constants and root-of-unity tables,
+// mixed-radix (Garner) tables of Section 3.4, and the workspace layout of one solve.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "modarith.h"
+
+namespace pd {
+
+constexpr int kMaxVars = 8;
+constexpr int kMaxN = 32;          // largest matrix order with a compiled elimination kernel
+constexpr int kMaxEntryDeg = 31;   // per-variable entry degree (evaluation kernel registers)
+constexpr int kMaxGrid = 4096;     // per-variable grid (interpolation tile in LDS)
+constexpr int kMaxPrimes = 32;     // reconstruction kernel registers
+
+// The descending table of primes p in (2^30, 2^31) with p = 1 mod 2^16.
+const std::vector<uint32_t>& prime_table();
+uint32_t primitive_root(uint32_t p);
+uint32_t powmod(uint32_t b, uint64_t e, uint32_t p);
+
+struct MatPlan {
+  int n = 0, k = 0;
+  int deg[kMaxVars] = {0}, D[kMaxVars] = {0}, N[kMaxVars] = {0}, m[kMaxVars] = {0};
+  int64_t G = 1, C = 1, T = 1, nent = 0;
+  int pn = 0, L = 0, prime_off = 0, det_lanes = 1;
+  std::vector<uint32_t> primes;
+  std::vector<PrimeConst> pc;
+  std::vector<uint8_t> entry_zero;  // empty when the plan was built without coefficients
+  double log2_bound_sq = 0;         // upper estimate of log2(B^2)
+
+  // device tables (inside the plan's single device allocation)
+  const PrimeConst* d_pc = nullptr;
+  const uint32_t* d_tw = nullptr;    // [pn][tw_stride]: forward w_v^t at tw_off[v] + t
+  const uint32_t* d_itw = nullptr;   // same layout, w_v^{-t}
+  int64_t tw_off[kMaxVars] = {0};
+  int64_t tw_stride = 0;
+  const uint32_t* d_gw = nullptr;    // [pn][pn] Garner weights (Montgomery): (p_0..p_{j-1}) mod p_i
+  const uint32_t* d_gc = nullptr;    // [pn] (p_0..p_{i-1})^{-1} mod p_i (Montgomery)
+  const uint32_t* d_mlimbs = nullptr;  // [L] M = p_0..p_{pn-1}
+  const uint32_t* d_hlimbs = nullptr;  // [L] (M-1)/2
+  const uint8_t* d_zero = nullptr;     // [nent] or null
+
+  // workspace layout (bytes, 256-aligned)
+  size_t off_res = 0, off_tmpA = 0, off_tmpB = 0, off_eval = 0, off_detv = 0, off_coef = 0,
+         off_iA = 0, off_iB = 0, ws_bytes = 0;
+  size_t in_bytes = 0, out_bytes = 0;
+};
+
+struct Plan {
+  std::vector<MatPlan> mats;
+  bool batch = false;
+  bool host_only = false;
+  int device = 0;
+  void* d_tables = nullptr;  // one device allocation for every table of every matrix
+  size_t ws_bytes = 0;       // workspace of one solve (a batch reuses it matrix by matrix)
+};
+
+struct ShapeIn {
+  int n, k;
+  int deg[kMaxVars];
+  int coeff_bits;
+};
+
+// Fills everything host-side (no device work). Returns an empty string on success or an
+// error message; *unsupported tells EUNSUPPORTED from EINVAL.
+std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t flags,
+                          MatPlan* out, bool* unsupported);
+
+// Serialises the device tables of every matrix, uploads them in one allocation and sets
+// the d_* pointers. Returns a HIP error code (0 = success).
+int upload_tables(Plan* plan);
+
+}  // namespace pd

@@ -1,0 +1,319 @@
+// C-ABI of the library (include/polydet.h): plan construction, queries and the solve that
+// enqueues the five stages of Algorithm 1 (Wei & Chen, arXiv 2010.12117) on one stream.
+#include "polydet.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.h"
+#include "plan.h"
+
+// Ring of event sets for POLYDET_STAGE_TIMING: a slot is read back (and its times added
+// to the sums) only before it is reused or when the caller asks for the times.
+struct StageTimer {
+  static constexpr int kSlots = 256;
+  static constexpr int kEvents = POLYDET_NUM_STAGES + 1;
+  hipEvent_t ev[kSlots][kEvents] = {};
+  bool pending[kSlots] = {};
+  int64_t next = 0, solves = 0;
+  double ms[POLYDET_NUM_STAGES] = {0};
+  bool ready = false;
+};
+
+struct polydet_plan_s {
+  pd::Plan plan;
+  StageTimer* timer = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+polydet_status fail(polydet_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+polydet_status hip_fail(hipError_t err, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorString(err);
+  return err == hipErrorOutOfMemory ? POLYDET_ENOMEM : POLYDET_EDEVICE;
+}
+
+polydet_status check_shape(const polydet_shape* s, pd::ShapeIn* out) {
+  if (!s) return fail(POLYDET_EINVAL, "shape is NULL");
+  out->n = s->n;
+  out->k = s->nvars;
+  out->coeff_bits = s->coeff_bits;
+  if (s->nvars < 0 || s->nvars > POLYDET_MAX_VARS) return fail(POLYDET_EINVAL, "nvars must be in 0..8");
+  for (int v = 0; v < POLYDET_MAX_VARS; ++v) out->deg[v] = v < s->nvars ? s->deg[v] : 0;
+  return POLYDET_OK;
+}
+
+polydet_status make_plan(const polydet_shape* shapes, int32_t count,
+                         const int64_t* const* host_coeffs, uint32_t flags, bool batch,
+                         polydet_plan_t* out) {
+  if (!out) return fail(POLYDET_EINVAL, "output plan pointer is NULL");
+  *out = nullptr;
+  if (!shapes || count < 1) return fail(POLYDET_EINVAL, "need at least one shape");
+  polydet_plan_s* h = new (std::nothrow) polydet_plan_s();
+  if (!h) return fail(POLYDET_ENOMEM, "host allocation failed");
+  h->plan.batch = batch;
+  h->plan.mats.resize(count);
+  for (int32_t i = 0; i < count; ++i) {
+    pd::ShapeIn s;
+    polydet_status st = check_shape(&shapes[i], &s);
+    if (st != POLYDET_OK) {
+      delete h;
+      return st;
+    }
+    bool unsupported = false;
+    const int64_t* hc = host_coeffs ? host_coeffs[i] : nullptr;
+    std::string err = pd::build_matplan(s, hc, flags, &h->plan.mats[i], &unsupported);
+    if (err.empty() && !pd::det_config_supported(s.n, h->plan.mats[i].det_lanes)) {
+      unsupported = true;
+      err = "no elimination kernel for this order and lane count";
+    }
+    if (!err.empty()) {
+      delete h;
+      return fail(unsupported ? POLYDET_EUNSUPPORTED : POLYDET_EINVAL,
+                  (batch ? "matrix " + std::to_string(i) + ": " : std::string()) + err);
+    }
+    h->plan.ws_bytes = std::max(h->plan.ws_bytes, h->plan.mats[i].ws_bytes);
+  }
+  h->plan.host_only = (flags & POLYDET_HOST_ONLY) != 0;
+  if (h->plan.host_only) {
+    *out = h;
+    g_last_error.clear();
+    return POLYDET_OK;
+  }
+  hipError_t e = hipGetDevice(&h->plan.device);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "hipGetDevice");
+  }
+  const int up = pd::upload_tables(&h->plan);
+  if (up != 0) {
+    delete h;
+    return hip_fail((hipError_t)up, "uploading plan tables");
+  }
+  if (flags & POLYDET_STAGE_TIMING) {
+    h->timer = new (std::nothrow) StageTimer();
+    if (!h->timer) {
+      polydet_plan_destroy(h);
+      return fail(POLYDET_ENOMEM, "host allocation failed");
+    }
+    for (auto& slot : h->timer->ev) {
+      for (auto& ev : slot) {
+        hipError_t ee = hipEventCreate(&ev);
+        if (ee != hipSuccess) {
+          polydet_plan_destroy(h);
+          return hip_fail(ee, "hipEventCreate");
+        }
+      }
+    }
+    h->timer->ready = true;
+  }
+  *out = h;
+  g_last_error.clear();
+  return POLYDET_OK;
+}
+
+hipError_t harvest(StageTimer* T, int slot) {
+  if (!T->pending[slot]) return hipSuccess;
+  hipError_t e = hipEventSynchronize(T->ev[slot][StageTimer::kEvents - 1]);
+  if (e != hipSuccess) return e;
+  for (int s = 0; s < POLYDET_NUM_STAGES; ++s) {
+    float ms = 0;
+    e = hipEventElapsedTime(&ms, T->ev[slot][s], T->ev[slot][s + 1]);
+    if (e != hipSuccess) return e;
+    T->ms[s] += ms;
+  }
+  T->pending[slot] = false;
+  T->solves += 1;
+  return hipSuccess;
+}
+
+polydet_status run_one(const pd::MatPlan& P, const int64_t* d_coeffs, uint32_t* d_out,
+                       uint8_t* ws, hipStream_t st, StageTimer* T) {
+  hipError_t e;
+  hipEvent_t* ev = nullptr;
+  if (T) {
+    const int slot = (int)(T->next++ % StageTimer::kSlots);
+    if ((e = harvest(T, slot)) != hipSuccess) return hip_fail(e, "stage timing");
+    ev = T->ev[slot];
+    T->pending[slot] = true;
+  }
+  auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
+  if ((e = mark(0)) != hipSuccess) return hip_fail(e, "stage timing");
+  if ((e = pd::run_reduce(P, d_coeffs, ws, st)) != hipSuccess) return hip_fail(e, "reduce");
+  if ((e = mark(1)) != hipSuccess) return hip_fail(e, "stage timing");
+  if ((e = pd::run_evaluate(P, ws, st)) != hipSuccess) return hip_fail(e, "evaluate");
+  if ((e = mark(2)) != hipSuccess) return hip_fail(e, "stage timing");
+  if ((e = pd::run_det(P, ws, st)) != hipSuccess) return hip_fail(e, "determinants");
+  if ((e = mark(3)) != hipSuccess) return hip_fail(e, "stage timing");
+  if ((e = pd::run_interpolate(P, ws, st)) != hipSuccess) return hip_fail(e, "interpolate");
+  if ((e = mark(4)) != hipSuccess) return hip_fail(e, "stage timing");
+  if ((e = pd::run_reconstruct(P, ws, d_out, st)) != hipSuccess) return hip_fail(e, "reconstruct");
+  if ((e = mark(5)) != hipSuccess) return hip_fail(e, "stage timing");
+  return POLYDET_OK;
+}
+
+polydet_status check_device(const pd::Plan& plan) {
+  if (plan.host_only) return fail(POLYDET_EINVAL, "a host-only plan cannot be solved");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != plan.device) {
+    return fail(POLYDET_EINVAL, "the current device differs from the plan's device " +
+                                    std::to_string(plan.device));
+  }
+  return POLYDET_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+polydet_status polydet_plan(const polydet_shape* shape, const int64_t* host_coeffs,
+                            uint32_t flags, polydet_plan_t* out) {
+  const int64_t* hc[1] = {host_coeffs};
+  return make_plan(shape, 1, hc, flags, false, out);
+}
+
+polydet_status polydet_plan_batch(const polydet_shape* shapes, int32_t count,
+                                  const int64_t* const* host_coeffs, uint32_t flags,
+                                  polydet_plan_t* out) {
+  return make_plan(shapes, count, host_coeffs, flags, true, out);
+}
+
+polydet_status polydet_plan_query(polydet_plan_t plan, int32_t index, polydet_plan_info* out) {
+  if (!plan || !out) return fail(POLYDET_EINVAL, "NULL plan or output");
+  if (index < 0 || index >= (int32_t)plan->plan.mats.size()) return fail(POLYDET_EINVAL, "index out of range");
+  const pd::MatPlan& P = plan->plan.mats[index];
+  std::memset(out, 0, sizeof(*out));
+  out->n = P.n;
+  out->nvars = P.k;
+  for (int v = 0; v < P.k; ++v) {
+    out->deg[v] = P.deg[v];
+    out->D[v] = P.D[v];
+    out->N[v] = P.N[v];
+  }
+  out->G = P.G;
+  out->ncoeff = P.C;
+  out->nterms = P.T;
+  out->pn = P.pn;
+  out->limbs = P.L;
+  out->det_lanes = P.det_lanes;
+  out->in_bytes = P.in_bytes;
+  out->out_bytes = P.out_bytes;
+  out->workspace_bytes = plan->plan.batch ? plan->plan.ws_bytes : P.ws_bytes;
+  out->off_eval = P.off_eval;
+  out->off_detv = P.off_detv;
+  out->off_coef = P.off_coef;
+  return POLYDET_OK;
+}
+
+polydet_status polydet_plan_primes(polydet_plan_t plan, int32_t index, uint32_t* out,
+                                   int32_t capacity) {
+  if (!plan || !out) return fail(POLYDET_EINVAL, "NULL plan or output");
+  if (index < 0 || index >= (int32_t)plan->plan.mats.size()) return fail(POLYDET_EINVAL, "index out of range");
+  const pd::MatPlan& P = plan->plan.mats[index];
+  if (capacity < P.pn) return fail(POLYDET_EINVAL, "capacity below the prime count");
+  std::memcpy(out, P.primes.data(), 4 * P.pn);
+  return POLYDET_OK;
+}
+
+polydet_status polydet_solve(polydet_plan_t plan, const int64_t* d_coeffs, uint32_t* d_out,
+                             void* d_workspace, size_t workspace_bytes, void* stream) {
+  if (!plan) return fail(POLYDET_EINVAL, "NULL plan");
+  if (plan->plan.batch) return fail(POLYDET_EINVAL, "batch plans are solved by polydet_solve_batch");
+  if (!d_coeffs || !d_out || !d_workspace) return fail(POLYDET_EINVAL, "NULL buffer");
+  const pd::MatPlan& P = plan->plan.mats[0];
+  if (workspace_bytes < P.ws_bytes) return fail(POLYDET_EINVAL, "workspace too small");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(POLYDET_EINVAL, "workspace must be 256-byte aligned");
+  polydet_status st = check_device(plan->plan);
+  if (st != POLYDET_OK) return st;
+  return run_one(P, d_coeffs, d_out, (uint8_t*)d_workspace, (hipStream_t)stream, plan->timer);
+}
+
+polydet_status polydet_solve_batch(polydet_plan_t plan, const int64_t* d_coeffs,
+                                   const int64_t* coeff_offsets, uint32_t* d_out,
+                                   const int64_t* out_offsets, void* d_workspace,
+                                   size_t workspace_bytes, void* stream) {
+  if (!plan) return fail(POLYDET_EINVAL, "NULL plan");
+  if (!d_coeffs || !d_out || !d_workspace || !coeff_offsets || !out_offsets)
+    return fail(POLYDET_EINVAL, "NULL buffer or offsets");
+  if (workspace_bytes < plan->plan.ws_bytes) return fail(POLYDET_EINVAL, "workspace too small");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(POLYDET_EINVAL, "workspace must be 256-byte aligned");
+  for (size_t i = 0; i < plan->plan.mats.size(); ++i) {
+    if (coeff_offsets[i] < 0 || out_offsets[i] < 0) return fail(POLYDET_EINVAL, "negative offset");
+  }
+  polydet_status st = check_device(plan->plan);
+  if (st != POLYDET_OK) return st;
+  for (size_t i = 0; i < plan->plan.mats.size(); ++i) {
+    st = run_one(plan->plan.mats[i], d_coeffs + coeff_offsets[i], d_out + out_offsets[i],
+                 (uint8_t*)d_workspace, (hipStream_t)stream, plan->timer);
+    if (st != POLYDET_OK) return st;
+  }
+  return POLYDET_OK;
+}
+
+polydet_status polydet_stage_times(polydet_plan_t plan, double ms[POLYDET_NUM_STAGES],
+                                   int64_t* solves) {
+  if (!plan || !ms) return fail(POLYDET_EINVAL, "NULL plan or output");
+  StageTimer* T = plan->timer;
+  if (!T) return fail(POLYDET_EINVAL, "the plan was made without POLYDET_STAGE_TIMING");
+  for (int slot = 0; slot < StageTimer::kSlots; ++slot) {
+    hipError_t e = harvest(T, slot);
+    if (e != hipSuccess) return hip_fail(e, "stage timing");
+  }
+  for (int s = 0; s < POLYDET_NUM_STAGES; ++s) {
+    ms[s] = T->ms[s];
+    T->ms[s] = 0;
+  }
+  if (solves) *solves = T->solves;
+  T->solves = 0;
+  return POLYDET_OK;
+}
+
+void polydet_plan_destroy(polydet_plan_t plan) {
+  if (!plan) return;
+  if (plan->timer) {
+    for (int slot = 0; slot < StageTimer::kSlots; ++slot) {
+      if (plan->timer->pending[slot]) (void)hipEventSynchronize(plan->timer->ev[slot][StageTimer::kEvents - 1]);
+      for (auto& ev : plan->timer->ev[slot]) {
+        if (ev) (void)hipEventDestroy(ev);
+      }
+    }
+    delete plan->timer;
+  }
+  if (plan->plan.d_tables) (void)hipFree(plan->plan.d_tables);
+  delete plan;
+}
+
+const char* polydet_status_string(polydet_status status) {
+  switch (status) {
+    case POLYDET_OK: return "ok";
+    case POLYDET_EINVAL: return "invalid argument";
+    case POLYDET_EUNSUPPORTED: return "unsupported by this build";
+    case POLYDET_ENOMEM: return "out of memory";
+    case POLYDET_EDEVICE: return "device error";
+    case POLYDET_ECANCELLED: return "cancelled";
+  }
+  return "unknown status";
+}
+
+const char* polydet_last_error(void) { return g_last_error.c_str(); }
+
+void polydet_limits(int32_t* max_n, int32_t* max_vars, int32_t* max_grid_per_var,
+                    int32_t* max_primes) {
+  if (max_n) *max_n = pd::kMaxN;
+  if (max_vars) *max_vars = pd::kMaxVars;
+  if (max_grid_per_var) *max_grid_per_var = pd::kMaxGrid;
+  if (max_primes) *max_primes = pd::kMaxPrimes;
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+"""Parity of the HIP path with the oracle (GPU). Every comparison is bit-exact: the path
+computes exact integers.
+
+Oracle A (Bareiss over Z[x]) covers small cases, oracle B (pointwise integer Bareiss with
+exact interpolation) covers the larger ones; stage checks compare the workspace after a
+solve with the oracle's modular steps at every or at sampled grid points."""
+import itertools
+import multiprocessing as mp
+import random
+
+import numpy as np
+import pytest
+
+import paper_2010_12117_amd as pdm
+from paper_2010_12117_amd import binding as B
+import workloads as W
+from oracle import det as OD
+from oracle import modular as OM
+from oracle import plan as PL
+from oracle import poly as P
+
+from helpers import box_to_dict, mont_to_plain, node_index, supported_lanes
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_solve(arr, flags=0, use_coeffs=True):
+    import torch
+    arr = np.ascontiguousarray(arr, dtype=np.int64)
+    n, deg = B.shape_of(arr)
+    pl = pdm.plan(n, deg, host_coeffs=arr if use_coeffs else None,
+                  coeff_bits=None if use_coeffs else B.coeff_bits_of(arr), flags=flags)
+    d = torch.from_numpy(arr).cuda()
+    out, ws = pdm.solve_device(pl, d)
+    torch.cuda.synchronize()
+    vals = B.limbs_to_ints(out.cpu().numpy())
+    box = tuple(x + 1 for x in pl.info["D"])
+    res = np.empty(len(vals), dtype=object)
+    for i, v in enumerate(vals):
+        res[i] = v
+    return res.reshape(box) if box else res.reshape(()), pl, ws
+
+
+def oracle_box(arr):
+    n, deg = B.shape_of(arr)
+    return OD.det_pointwise(arr, PL.det_degree_bound_from_shape(n, deg))
+
+
+def oracle_poly(arr):
+    n, deg = B.shape_of(arr)
+    return OD.det_bareiss_poly(P.matrix_from_array(arr, n, len(deg)), len(deg))
+
+
+@pytest.fixture(scope="module")
+def pool():
+    ctx = mp.get_context("spawn")
+    p = ctx.Pool(min(16, mp.cpu_count()))
+    yield p
+    p.close()
+    p.join()
+
+
+def test_config1_bit_exact():
+    arr = W.config1()
+    got, pl, _ = gpu_solve(arr)
+    assert box_to_dict(got) == oracle_poly(arr)
+    assert box_to_dict(got) == box_to_dict(oracle_box(arr))
+
+
+CASES = [
+    # (n, deg, amp, zero_prob, seed)
+    (1, (3, 2), 50, 0.0, 1), (2, (1, 1), 9, 0.0, 2), (3, (2,), 100, 0.3, 3),
+    (4, (1, 1, 1), 7, 0.3, 4), (5, (2, 1), 1000, 0.4, 5), (6, (1, 1), 3, 0.5, 6),
+    (3, (), 10 ** 6, 0.2, 7), (7, (1,), 2 ** 20, 0.2, 8), (4, (5, 3), 30, 0.1, 9),
+    (2, (7, 1, 1, 1), 5, 0.0, 10), (3, (1, 1, 1, 1, 1), 4, 0.0, 11), (8, (1, 1), 2, 0.6, 12),
+]
+
+
+@pytest.mark.parametrize("n,deg,amp,zp,seed", CASES)
+def test_small_random_cases(n, deg, amp, zp, seed):
+    rng = np.random.default_rng(seed)
+    arr = W.random_matrix(rng, n, deg, -amp, amp, zero_prob=zp)
+    got, _, _ = gpu_solve(arr)
+    expect = oracle_poly(arr) if n <= 5 else box_to_dict(oracle_box(arr))
+    assert box_to_dict(got) == expect
+
+
+@pytest.mark.parametrize("n", list(range(1, 33)))
+def test_every_order_default_lanes(n):
+    rng = np.random.default_rng(1000 + n)
+    arr = W.random_matrix(rng, n, (1,), -20, 20, zero_prob=0.2)
+    got, _, _ = gpu_solve(arr)
+    assert box_to_dict(got) == box_to_dict(oracle_box(arr))
+
+
+LANE_CASES = [(n, gl) for n in (2, 4, 7, 8, 12, 13, 16, 17, 22, 24, 25, 31, 32)
+              for gl in supported_lanes(n)]
+
+
+@pytest.mark.parametrize("n,lanes", LANE_CASES)
+def test_every_lane_mapping(n, lanes):
+    rng = np.random.default_rng(2000 + 40 * n + lanes)
+    arr = W.random_matrix(rng, n, (1,), -9, 9, zero_prob=0.35)
+    log2 = {1: 0, 2: 1, 4: 2, 8: 3, 16: 4}[lanes]
+    got, pl, _ = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2))
+    assert pl.info["det_lanes"] == lanes
+    assert box_to_dict(got) == box_to_dict(oracle_box(arr))
+
+
+def test_integer_matrices_extreme_values():
+    # k = 0: the plain integer determinant, with int64 extremes
+    rng = random.Random(5)
+    for n in [1, 2, 3, 5, 8, 12]:
+        M = [[rng.choice([0, 1, -1, 2 ** 63 - 1, -(2 ** 63), rng.randint(-2 ** 62, 2 ** 62)])
+              for _ in range(n)] for _ in range(n)]
+        arr = np.array(M, dtype=np.int64)
+        got, _, _ = gpu_solve(arr)
+        assert int(got[()]) == OD.det_bareiss_int(M)
+    for n in [20, 32]:
+        M = [[rng.randint(-2 ** 20, 2 ** 20) for _ in range(n)] for _ in range(n)]
+        got, _, _ = gpu_solve(np.array(M, dtype=np.int64))
+        assert int(got[()]) == OD.det_bareiss_int(M)
+
+
+def test_singular_and_structured():
+    rng = np.random.default_rng(44)
+    # duplicated row -> 0
+    a = W.random_matrix(rng, 6, (2, 1), -30, 30)
+    a[3] = a[1]
+    got, _, _ = gpu_solve(a)
+    assert box_to_dict(got) == {}
+    # zero matrix and zero column
+    z = np.zeros((5, 5, 2, 2), dtype=np.int64)
+    got, _, _ = gpu_solve(z)
+    assert box_to_dict(got) == {}
+    b = W.random_matrix(rng, 5, (1, 1), -5, 5)
+    b[:, 2] = 0
+    got, _, _ = gpu_solve(b)
+    assert box_to_dict(got) == {}
+    # permutation matrix of constants (every pivot needs an exchange)
+    perm = [3, 0, 4, 1, 2]
+    c = np.zeros((5, 5, 1), dtype=np.int64)
+    for i, j in enumerate(perm):
+        c[i, j, 0] = 1
+    got, _, _ = gpu_solve(c)
+    assert box_to_dict(got) == oracle_poly(c)
+    # triangular with polynomial diagonal
+    t = np.triu(np.ones((6, 6), dtype=np.int64))[:, :, None, None] * \
+        W.random_matrix(rng, 6, (1, 2), -4, 4)
+    got, _, _ = gpu_solve(t)
+    assert box_to_dict(got) == box_to_dict(oracle_box(t))
+
+
+def test_invariance_to_primes_and_bound():
+    arr = W.random_matrix(np.random.default_rng(8), 6, (2, 2), -500, 500, zero_prob=0.3)
+    base, pl, _ = gpu_solve(arr)
+    pn = pl.info["pn"]
+    more, _, _ = gpu_solve(arr, flags=pdm.FORCE_PN(pn + 2))
+    disjoint, _, _ = gpu_solve(arr, flags=pdm.PRIME_OFFSET(pn + 5))
+    worst, plw, _ = gpu_solve(arr, use_coeffs=False)
+    assert plw.info["pn"] >= pn
+    for other in (more, disjoint, worst):
+        assert box_to_dict(other) == box_to_dict(base)
+
+
+def test_stages_against_oracle_steps():
+    # S2 values at every node, S3 determinants at every node, S4 coefficients mod p
+    import torch
+    arr = W.random_matrix(np.random.default_rng(9), 3, (2, 1), -40, 40, zero_prob=0.2)
+    got, pl, ws = gpu_solve(arr, flags=pdm.FORCE_PN(2))
+    info = pl.info
+    n, k = 3, 2
+    N = info["N"]
+    G = info["G"]
+    w = ws.cpu().numpy()
+    ev = w[info["off_eval"]:info["off_eval"] + 4 * info["pn"] * n * n * G].view(np.uint32)
+    ev = ev.reshape(info["pn"], n * n, G)
+    dv = w[info["off_detv"]:info["off_detv"] + 4 * info["pn"] * G].view(np.uint32)
+    dv = dv.reshape(info["pn"], G)
+    cf = w[info["off_coef"]:info["off_coef"] + 4 * info["pn"] * info["ncoeff"]].view(np.uint32)
+    cf = cf.reshape(info["pn"], info["ncoeff"])
+    M = P.matrix_from_array(arr, n, k)
+    exact = oracle_poly(arr)
+    box = tuple(d + 1 for d in info["D"])
+    for q, p in enumerate(info["primes"]):
+        omegas = [PL.root_of_unity(p, x) for x in N]
+        for j in itertools.product(*[range(x) for x in N]):
+            idx = node_index(j, N)
+            A = [[OM.evaluate_at_node(M[r][c], p, omegas, j) for c in range(n)] for r in range(n)]
+            for r in range(n):
+                for c in range(n):
+                    assert mont_to_plain(ev[q, r * n + c, idx], p) == A[r][c]
+            assert mont_to_plain(dv[q, idx], p) == OM.det_mod(A, p)
+        for e in itertools.product(*[range(b) for b in box]):
+            ci = node_index(e, box)
+            # the interpolation leaves the factor G for the reconstruction
+            assert mont_to_plain(cf[q, ci], p) == exact.get(e, 0) * G % p
+
+
+def test_config2_bit_exact(pool):
+    arr = W.config2()
+    got, pl, _ = gpu_solve(arr)
+    assert pl.info["pn"] == 7 and pl.info["N"] == (64, 64, 64)
+    expect = OD.det_pointwise(arr, PL.det_degree_bound_from_shape(12, (3, 3, 3)), pool=pool)
+    assert box_to_dict(got) == box_to_dict(expect)
+
+
+def test_config3a_sylvester_bit_exact(pool):
+    arr = W.config3a()
+    got, pl, _ = gpu_solve(arr)
+    assert pl.info["N"] == (128, 128)
+    expect = OD.det_pointwise(arr, PL.det_degree_bound_from_shape(22, (4, 4)), pool=pool)
+    assert box_to_dict(got) == box_to_dict(expect)
+
+
+def test_config3b_resultant_closed_form():
+    S, ff, gf = W.config3b()
+    got, _, _ = gpu_solve(S)
+    expect = P.const(1, 2)
+    for a, b in ff:
+        for c, d in gf:
+            term = P.sub(P.mul(box_to_dict(b), box_to_dict(c)), P.mul(box_to_dict(a), box_to_dict(d)))
+            expect = P.mul(expect, term)
+    assert box_to_dict(got) == expect

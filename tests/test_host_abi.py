@@ -1,0 +1,162 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared entry point, and its
+host-side plan (degree bound, grid, prime choice, limbs, errors) agrees with the oracle's
+plan quantities. No GPU work is launched here."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2010_12117_amd as pdm
+from paper_2010_12117_amd import binding as B
+import workloads as W
+from oracle import plan as PL
+
+from helpers import declared_functions
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pdm.load_library()
+    names = declared_functions()
+    assert "polydet_solve_batch" in names and "polydet_plan" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_limits():
+    lib = pdm.load_library()
+    for st in range(6):
+        assert lib.polydet_status_string(st)
+    lim = pdm.limits()
+    assert lim["max_n"] >= 32 and lim["max_vars"] == 8 and lim["max_primes"] >= 27
+
+
+def _oracle_pn(arr):
+    return PL.num_primes(PL.hadamard_bound_sq(arr))
+
+
+@pytest.mark.parametrize("which", ["c1", "c2", "c3a", "c3b", "k0", "n1"])
+def test_host_plan_matches_oracle_plan(which):
+    if which == "c1":
+        arr = W.config1()
+    elif which == "c2":
+        arr = W.config2()
+    elif which == "c3a":
+        arr = W.config3a()
+    elif which == "c3b":
+        arr = W.config3b()[0]
+    elif which == "k0":
+        arr = np.array([[2 ** 62, -(2 ** 62)], [3, 2 ** 61]], dtype=np.int64)
+    else:
+        arr = np.arange(1, 10, dtype=np.int64).reshape(1, 1, 9)
+    n, deg = B.shape_of(arr)
+    pl = pdm.plan(n, deg, host_coeffs=arr, flags=pdm.HOST_ONLY)
+    info = pl.info
+    D = PL.det_degree_bound_from_shape(n, deg)
+    assert list(info["D"]) == D
+    assert list(info["N"]) == PL.grid_sizes(D)
+    assert info["G"] == int(np.prod(PL.grid_sizes(D))) if D else info["G"] == 1
+    pn0 = _oracle_pn(arr)
+    # the library's bound carries a margin of at most one extra prime
+    assert pn0 <= info["pn"] <= pn0 + 1
+    assert info["primes"] == PL.ntt_primes(info["pn"])
+    M = 1
+    for p in info["primes"]:
+        M *= p
+    assert info["limbs"] == PL.limbs_for(M)
+
+
+def test_survey_sizes():
+    # sizes of the paper-shaped workloads (grid, primes)
+    c2 = pdm.plan(12, (3, 3, 3), host_coeffs=W.config2(), flags=pdm.HOST_ONLY).info
+    assert c2["N"] == (64, 64, 64) and c2["pn"] == 7 and c2["ncoeff"] == 37 ** 3
+    c3 = pdm.plan(22, (4, 4), host_coeffs=W.config3a(), flags=pdm.HOST_ONLY).info
+    assert c3["N"] == (128, 128) and c3["pn"] == 15
+    c1 = pdm.plan(4, (2, 2), host_coeffs=W.config1(), flags=pdm.HOST_ONLY).info
+    assert c1["N"] == (16, 16) and c1["pn"] == 1
+
+
+def test_worst_case_bound_dominates_data_bound():
+    rng = np.random.default_rng(3)
+    for _ in range(10):
+        n = int(rng.integers(1, 20))
+        k = int(rng.integers(0, 4))
+        deg = tuple(int(x) for x in rng.integers(0, 4, size=k))
+        arr = W.random_matrix(rng, n, deg, -1000, 1000)
+        a = pdm.plan(n, deg, host_coeffs=arr, flags=pdm.HOST_ONLY).info
+        b = pdm.plan(n, deg, coeff_bits=10, flags=pdm.HOST_ONLY).info
+        assert b["pn"] >= a["pn"]
+        assert a["D"] == b["D"] and a["G"] == b["G"]
+
+
+def test_forced_prime_count_and_offset():
+    arr = W.config1()
+    base = pdm.plan(4, (2, 2), host_coeffs=arr, flags=pdm.HOST_ONLY).info
+    forced = pdm.plan(4, (2, 2), host_coeffs=arr, flags=pdm.HOST_ONLY | pdm.FORCE_PN(5)).info
+    assert forced["pn"] == 5 and forced["primes"] == PL.ntt_primes(5)
+    off = pdm.plan(4, (2, 2), host_coeffs=arr,
+                   flags=pdm.HOST_ONLY | pdm.PRIME_OFFSET(3)).info
+    assert off["primes"] == PL.ntt_primes(3 + off["pn"])[3:]
+    big = W.config2()
+    with pytest.raises(pdm.PolydetError) as e:
+        pdm.plan(12, (3, 3, 3), host_coeffs=big, flags=pdm.HOST_ONLY | pdm.FORCE_PN(2))
+    assert e.value.status == B.EINVAL
+
+
+@pytest.mark.parametrize("n,deg,status", [
+    (0, (1,), B.EINVAL), (-3, (), B.EINVAL), (3, (1,) * 9, B.EINVAL), (3, (-1, 2), B.EINVAL),
+    (33, (1,), B.EUNSUPPORTED), (3, (32,), B.EUNSUPPORTED)])
+def test_plan_errors(n, deg, status):
+    lib = pdm.load_library()
+    s = B.Shape()
+    s.n = n
+    s.nvars = len(deg)
+    for v, d in enumerate(deg[:8]):
+        s.deg[v] = d
+    s.coeff_bits = 10
+    h = ctypes.c_void_p()
+    st = lib.polydet_plan(ctypes.byref(s), None, pdm.HOST_ONLY, ctypes.byref(h))
+    assert st == status
+    assert not h.value
+    assert lib.polydet_last_error()
+
+
+def test_bad_coeff_bits_and_null_arguments():
+    lib = pdm.load_library()
+    s = B.make_shape(3, (1,), 64)
+    h = ctypes.c_void_p()
+    assert lib.polydet_plan(ctypes.byref(s), None, pdm.HOST_ONLY, ctypes.byref(h)) == B.EINVAL
+    assert lib.polydet_plan(None, None, pdm.HOST_ONLY, ctypes.byref(h)) == B.EINVAL
+    assert lib.polydet_plan_query(None, 0, None) == B.EINVAL
+    assert lib.polydet_plan_batch(None, 0, None, pdm.HOST_ONLY, ctypes.byref(h)) == B.EINVAL
+
+
+def test_host_only_plan_cannot_be_solved():
+    lib = pdm.load_library()
+    pl = pdm.plan(4, (2, 2), coeff_bits=4, flags=pdm.HOST_ONLY)
+    dummy = ctypes.c_void_p(256)
+    st = lib.polydet_solve(pl.handle, dummy, dummy, dummy, pl.info["workspace_bytes"], None)
+    assert st == B.EINVAL
+    small = lib.polydet_solve(pl.handle, dummy, dummy, dummy, 16, None)
+    assert small == B.EINVAL
+
+
+def test_batch_plan_host_only():
+    mats = W.config4(count=16)
+    pl = pdm.plan_batch(mats, flags=pdm.HOST_ONLY)
+    assert pl.count == 16
+    for a, info in zip(mats, pl.infos):
+        n, deg = B.shape_of(a)
+        assert info["n"] == n and tuple(info["deg"]) == deg
+        pn0 = _oracle_pn(a)
+        assert pn0 <= info["pn"] <= pn0 + 1
+
+
+def test_limb_decoding():
+    vals = [0, 1, -1, 2 ** 31, -(2 ** 31), 2 ** 95 - 1, -(2 ** 95)]
+    L = 3
+    rows = []
+    for v in vals:
+        u = v % (1 << (32 * L))
+        rows.append([(u >> (32 * l)) & 0xFFFFFFFF for l in range(L)])
+    arr = np.array(rows, dtype=np.uint32)
+    assert B.limbs_to_ints(arr) == vals
