@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="before the timed loop, copy 1 GiB device to device once (a kernel of "
+                         "known traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the determinant path is a single-GPU "
@@ -91,6 +94,12 @@ def main():
     ws = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         pdm.solve_device(pl, d_coeffs, out, ws)
     torch.cuda.synchronize()

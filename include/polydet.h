@@ -69,6 +69,11 @@ typedef struct polydet_shape {
   int32_t coeff_bits;
 } polydet_shape;
 
+/* POLYDET_UNFUSED_EVAL: write the full evaluation tensor (off_eval) and run the
+ * elimination from it, in the paper's stage order. By default the evaluation along the
+ * first variable is fused into the elimination kernel and that tensor is never written
+ * (off_eval is then SIZE_MAX). Results are identical either way. */
+#define POLYDET_UNFUSED_EVAL ((uint32_t)1u)
 /* Plan flags. POLYDET_FORCE_PN(x): use exactly x primes (x >= the number the bound needs,
  * else EINVAL). POLYDET_PRIME_OFFSET(x): skip the first x primes of the table (a disjoint
  * prime set; the result does not depend on it). */
@@ -89,6 +94,7 @@ typedef struct polydet_shape {
 /* What a plan needs and produces. Workspace offsets (bytes) locate the intermediate stages
  * for inspection after a solve on the same stream has completed:
  *   off_eval : uint32 [pn][n*n][G]  entry values at the grid points, Montgomery form
+ *              (written only by plans made with POLYDET_UNFUSED_EVAL or with nvars = 0)
  *              (x * 2^32 mod p); point index = natural multi-index (j_1 slowest), node
  *              (w_1^j_1, ..., w_k^j_k) with w_v = g^((p-1)/N[v]), g the least primitive
  *              root mod p;
@@ -105,11 +111,16 @@ typedef struct polydet_plan_info {
   int32_t pn;         /* primes */
   int32_t limbs;      /* 32-bit limbs per output coefficient */
   int32_t det_lanes;  /* lanes that cooperate on one determinant */
-  int32_t reserved;
+  int32_t det_sign;   /* +1 or -1: see row_order */
   size_t in_bytes;    /* 8 * n * n * nterms */
   size_t out_bytes;   /* 4 * ncoeff * limbs */
   size_t workspace_bytes;
   size_t off_eval, off_detv, off_coef;
+  /* The kernels work on the matrix with its rows reordered so that no pivot is zero for
+   * structural reasons (from the zero entries of host_coeffs; identity without them): row i
+   * of that matrix is input row row_order[i] (i < n). Stage values at off_eval and off_detv
+   * refer to the reordered matrix, whose determinant is det_sign times det M. */
+  uint8_t row_order[32];
 } polydet_plan_info;
 
 typedef struct polydet_plan_s* polydet_plan_t;

@@ -32,6 +32,7 @@ def PRIME_OFFSET(x: int) -> int:
     return (x & 0x3FF) << 20
 
 
+UNFUSED_EVAL = 1
 HOST_ONLY = 1 << 31
 STAGE_TIMING = 1 << 30
 STAGES = ("reduce", "evaluate", "determinants", "interpolate", "reconstruct")
@@ -54,10 +55,11 @@ class PlanInfo(ctypes.Structure):
                 ("N", ctypes.c_int32 * MAX_VARS), ("G", ctypes.c_int64),
                 ("ncoeff", ctypes.c_int64), ("nterms", ctypes.c_int64),
                 ("pn", ctypes.c_int32), ("limbs", ctypes.c_int32),
-                ("det_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("det_lanes", ctypes.c_int32), ("det_sign", ctypes.c_int32),
                 ("in_bytes", ctypes.c_size_t), ("out_bytes", ctypes.c_size_t),
                 ("workspace_bytes", ctypes.c_size_t), ("off_eval", ctypes.c_size_t),
-                ("off_detv", ctypes.c_size_t), ("off_coef", ctypes.c_size_t)]
+                ("off_detv", ctypes.c_size_t), ("off_coef", ctypes.c_size_t),
+                ("row_order", ctypes.c_uint8 * 32)]
 
 
 EXPORTS = ["polydet_plan", "polydet_plan_batch", "polydet_plan_query", "polydet_plan_primes",
@@ -157,6 +159,7 @@ class Plan:
         d = {f: getattr(info, f) for f, _ in PlanInfo._fields_}
         for f in ("deg", "D", "N"):
             d[f] = tuple(getattr(info, f)[v] for v in range(k))
+        d["row_order"] = tuple(int(info.row_order[i]) for i in range(info.n))
         arr = (ctypes.c_uint32 * max(1, info.pn))()
         _check(lib.polydet_plan_primes(self._h, i, arr, info.pn))
         d["primes"] = [int(arr[j]) for j in range(info.pn)]

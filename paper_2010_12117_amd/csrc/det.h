@@ -9,6 +9,23 @@
 
 namespace pd {
 
+// Arguments of the fused evaluation + elimination launch (det_impl.h, det_fused_kernel).
+struct FusedDetArgs {
+  const uint32_t* pre;   // [pn][n*n][m0][R]
+  uint32_t* detv;        // [pn][N0 * R]
+  int64_t R;             // grid points of the other variables
+  int N0, m0;            // grid size and coefficient count of the first variable
+  int Q, S;              // points per LDS tile, first-variable values per block
+  const uint32_t* tw0;   // w_0^t (Montgomery), t < N0, at prime * tw_stride
+  int64_t tw_stride;
+  const PrimeConst* pcs;
+  const uint8_t* zero;   // [n*n] zero-entry flags or null
+  int pn;
+};
+
+template <int N, int GL>
+hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st);
+
 template <int N, int GL>
 hipError_t det_launch(const uint32_t* eval, uint32_t* detv, int64_t npts, int pn,
                       const PrimeConst* pcs, hipStream_t st);

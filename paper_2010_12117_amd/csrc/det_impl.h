@@ -1,5 +1,5 @@
-// Elimination kernel of the DET stage, included by the det_part.hip translation units that
-// instantiate it for each (order, lanes-per-matrix) pair (det.h declares the launchers).
+// Elimination kernels of the DET stage, included by the det_part.hip translation units that
+// instantiate them for each (order, lanes-per-matrix) pair (det.h declares the launchers).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,6 +10,7 @@
 namespace pd {
 
 constexpr int kDetBlock = 256;
+constexpr int kEvalChunk = 8;  // entries per scheduling window of the fused evaluation
 
 // ------------------------------------------------------------------------------------
 // S3: determinant of the n x n matrix at every (prime, grid point).
@@ -40,32 +41,12 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
   }
 }
 
+// Determinant (Montgomery form) of the matrix held by the lane group; every lane of the
+// group returns it. All lanes of the wave must call this together (lane shuffles).
 template <int N, int GL>
-__global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restrict__ eval,
-                                                     uint32_t* __restrict__ detv, int64_t npts,
-                                                     const PrimeConst* __restrict__ pcs) {
+__device__ __forceinline__ uint32_t eliminate(uint32_t (&a)[(N + GL - 1) / GL][N], uint32_t p,
+                                              uint32_t pinv, uint32_t one) {
   constexpr int C = (N + GL - 1) / GL;
-  constexpr int PER_BLOCK = kDetBlock / GL;
-  const int prime = blockIdx.y;
-  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
-  const int t = (int)(threadIdx.x % GL);
-  const int64_t pt = (int64_t)blockIdx.x * PER_BLOCK + threadIdx.x / GL;
-  const bool valid = pt < npts;
-  const int64_t ptc = valid ? pt : npts - 1;
-  const uint32_t* src = eval + (int64_t)prime * N * N * npts + ptc;
-
-  uint32_t a[C][N];
-#pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const int col = c * GL + t;
-    const int colc = col < N ? col : N - 1;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const uint32_t v = src[(int64_t)(i * N + colc) * npts];
-      a[c][i] = col < N ? v : 0u;
-    }
-  }
-
   uint32_t flip = 0;
   bool dead = false;
   uint32_t e = one, Q = one;
@@ -109,8 +90,148 @@ __global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restri
   dead = dead || (last == 0u);
   uint32_t d = mm(last, minv(Q, one, p, pinv), p, pinv);
   if (flip) d = negm(d, p);
-  if (dead) d = 0u;
+  return dead ? 0u : d;
+}
+
+// Unfused form: the matrix at each point is read from the full evaluation tensor
+// eval[pn][n*n][npts].
+template <int N, int GL>
+__global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restrict__ eval,
+                                                        uint32_t* __restrict__ detv, int64_t npts,
+                                                        const PrimeConst* __restrict__ pcs) {
+  constexpr int C = (N + GL - 1) / GL;
+  constexpr int PER_BLOCK = kDetBlock / GL;
+  const int prime = blockIdx.y;
+  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
+  const int t = (int)(threadIdx.x % GL);
+  const int64_t pt = (int64_t)blockIdx.x * PER_BLOCK + threadIdx.x / GL;
+  const bool valid = pt < npts;
+  const int64_t ptc = valid ? pt : npts - 1;
+  const uint32_t* src = eval + (int64_t)prime * N * N * npts + ptc;
+
+  uint32_t a[C][N];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int col = c * GL + t;
+    const int colc = col < N ? col : N - 1;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const uint32_t v = src[(int64_t)(i * N + colc) * npts];
+      a[c][i] = col < N ? v : 0u;
+    }
+  }
+  const uint32_t d = eliminate<N, GL>(a, p, pinv, one);
   if (valid && t == 0) detv[(int64_t)prime * npts + pt] = d;
+}
+
+// Fused form: the last evaluation axis (the first variable, whose grid index j0 is the
+// slowest) runs inside the elimination kernel, so the full evaluation tensor never exists.
+// pre[pn][n*n][m0][R] holds every entry already evaluated along the other variables (R
+// points) with its m0 coefficients in the first variable. A block stages the columns
+// r0 .. r0+Q-1 of every nonzero entry in LDS as tile[m][q][e] (row stride NEP = n*n | 1, odd,
+// so lanes reading different q hit different banks and the entry index is an immediate
+// offset) and then, for S values of j0, each lane group rebuilds its matrix at the point
+// (j0, r0 + q) by Horner's rule in w0^j0 (the evaluation of Section 2 along x1) and
+// eliminates it. Point index = j0 R + r.
+template <int N, int GL>
+__global__ __launch_bounds__(kDetBlock) void det_fused_kernel(
+    const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, int64_t R, int N0, int m0,
+    int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
+  constexpr int C = (N + GL - 1) / GL;
+  constexpr int NE = N * N;
+  constexpr int NEP = NE | 1;
+  extern __shared__ uint32_t tile[];  // [m0][Q][NEP]
+  const int prime = blockIdx.y;
+  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
+  const int64_t rtiles = (R + Q - 1) / Q;
+  const int64_t r0 = (blockIdx.x % rtiles) * Q;
+  const int jbase = (int)(blockIdx.x / rtiles) * S;
+  const uint32_t* src = pre + (int64_t)prime * NE * m0 * R;
+
+  const int mq = m0 * Q;
+  for (int idx = threadIdx.x; idx < NE * mq; idx += kDetBlock) {
+    const int e = idx / mq;
+    const int rem = idx - e * mq;  // = m Q + q
+    const int q = rem % Q;
+    const int m = rem / Q;
+    uint32_t v = 0u;
+    if (!(zero && zero[e]) && r0 + q < R) v = src[((int64_t)e * m0 + m) * R + r0 + q];
+    tile[rem * NEP + e] = v;
+  }
+  __syncthreads();
+
+  const int t = (int)(threadIdx.x % GL);
+  const int slot = (int)(threadIdx.x / GL);
+  const int q = slot % Q;
+  const int J = (kDetBlock / GL) / Q;
+  const int jj = slot / Q;
+  const bool qvalid = r0 + q < R;
+  const uint32_t* w0 = tw0 + (int64_t)prime * tw_stride;
+  // column offset of the lane within its slot, clamped for the padded columns of the last
+  // slot (their registers are zeroed after the evaluation)
+  const int tl = t < N - (C - 1) * GL ? t : N - 1 - (C - 1) * GL;
+  const int dl = tl - t;
+
+  for (int j = jbase; j < jbase + S && j < N0; j += J) {
+    const int j0 = j + jj;
+    const bool valid = qvalid && j0 < N0 && j0 < jbase + S;
+    const int j0c = j0 < N0 ? j0 : N0 - 1;
+    uint32_t a[C][N];
+    // a[c][i] = sum_{m < m0} x_m w0^{m j0}, two terms per reduction (mm2). With m0 even the
+    // constant term pairs with x_1 (its factor is R mod p, the representative of 1); with
+    // m0 odd it stands alone. The loop over m is uniform and sits outside the unrolled
+    // loops over the entries held by the lane.
+    int mstart;
+    if ((m0 & 1) == 0) {
+      const uint32_t w1 = w0[j0c & (N0 - 1)];
+      const uint32_t* r0w = tile + q * NEP + t;
+      const uint32_t* r1w = r0w + Q * NEP;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const int off = i * N + c * GL + (c == C - 1 ? dl : 0);
+          a[c][i] = mm2(r0w[off], one, r1w[off], w1, p, pinv);
+          if ((c * N + i) % kEvalChunk == kEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      mstart = 2;
+    } else {
+      const uint32_t* r0w = tile + q * NEP + t;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) a[c][i] = r0w[i * N + c * GL + (c == C - 1 ? dl : 0)];
+      }
+      mstart = 1;
+    }
+    for (int m = mstart; m < m0; m += 2) {
+      const uint32_t wa = w0[(m * j0c) & (N0 - 1)];
+      const uint32_t wb = w0[((m + 1) * j0c) & (N0 - 1)];
+      const uint32_t* ra = tile + (m * Q + q) * NEP + t;
+      const uint32_t* rb = ra + Q * NEP;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          const int off = i * N + c * GL + (c == C - 1 ? dl : 0);
+          a[c][i] = addm(a[c][i], mm2(ra[off], wa, rb[off], wb, p, pinv), p);
+          // bound the scheduler's window so that the LDS reads (one register each) are
+          // not all hoisted ahead of the arithmetic
+          if ((c * N + i) % kEvalChunk == kEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    if constexpr (C * GL > N) {
+      if ((C - 1) * GL + t >= N) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) a[C - 1][i] = 0u;
+      }
+    }
+    const uint32_t d = eliminate<N, GL>(a, p, pinv, one);
+    if (valid && t == 0) detv[(int64_t)prime * N0 * R + (int64_t)j0 * R + r0 + q] = d;
+  }
 }
 
 template <int N, int GL>
@@ -120,6 +241,17 @@ hipError_t det_launch(const uint32_t* eval, uint32_t* detv, int64_t npts, int pn
   const int64_t bx = (npts + per_block - 1) / per_block;
   hipLaunchKernelGGL((det_kernel<N, GL>), dim3((unsigned)bx, (unsigned)pn), dim3(kDetBlock), 0, st,
                      eval, detv, npts, pcs);
+  return hipGetLastError();
+}
+
+template <int N, int GL>
+hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st) {
+  const int64_t rtiles = (f.R + f.Q - 1) / f.Q;
+  const int64_t jtiles = (f.N0 + f.S - 1) / f.S;
+  const size_t lds = (size_t)((N * N) | 1) * f.m0 * f.Q * sizeof(uint32_t);
+  hipLaunchKernelGGL((det_fused_kernel<N, GL>), dim3((unsigned)(rtiles * jtiles), (unsigned)f.pn),
+                     dim3(kDetBlock), lds, st, f.pre, f.detv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0,
+                     f.tw_stride, f.pcs, f.zero);
   return hipGetLastError();
 }
 

@@ -10,7 +10,8 @@ namespace pd {
 
 #define PD_DET(N, GL)                                                                  \
   template hipError_t det_launch<N, GL>(const uint32_t*, uint32_t*, int64_t, int,     \
-                                        const PrimeConst*, hipStream_t);
+                                        const PrimeConst*, hipStream_t);              \
+  template hipError_t det_fused_launch<N, GL>(const FusedDetArgs&, hipStream_t);
 
 #if DET_PART == 0
 PD_DET(1, 1) PD_DET(2, 1) PD_DET(3, 1) PD_DET(4, 1) PD_DET(5, 1) PD_DET(6, 1)

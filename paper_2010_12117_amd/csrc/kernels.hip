@@ -27,12 +27,17 @@ inline unsigned blocks_for(int64_t work, int per_block = kBlock) {
 // S1: int64 coefficient -> representative of (c mod p) for every prime.
 // |c| = hi 2^32 + lo with hi <= 2^31, so c~ = mm(hi, R^3) + mm(lo, R^2), negated for c < 0.
 // ------------------------------------------------------------------------------------
+// Entries are written in elimination row order: input row r goes to row rowdest[r].
 __global__ __launch_bounds__(kBlock) void reduce_kernel(const int64_t* __restrict__ in,
                                                         uint32_t* __restrict__ out,
-                                                        int64_t count, int pn,
+                                                        int64_t count, int pn, int n, int64_t T,
+                                                        const int32_t* __restrict__ rowdest,
                                                         const PrimeConst* __restrict__ pcs) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= count) return;
+  const int64_t e = i / T;
+  const int row = (int)(e / n), col = (int)(e - (int64_t)row * n);
+  const int64_t dst = ((int64_t)rowdest[row] * n + col) * T + (i - e * T);
   const int64_t c = in[i];
   const bool neg = c < 0;
   const uint64_t a = neg ? (uint64_t)(-(c + 1)) + 1u : (uint64_t)c;
@@ -41,7 +46,7 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(const int64_t* __restric
     const PrimeConst P = pcs[q];
     uint32_t r = addm(mm(hi, P.r3, P.p, P.pinv), mm(lo, P.r2, P.p, P.pinv), P.p);
     if (neg) r = negm(r, P.p);
-    out[(int64_t)q * count + i] = r;
+    out[(int64_t)q * count + dst] = r;
   }
 }
 
@@ -100,13 +105,13 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
 // and writes the first D_v + 1 outputs of each line:
 //   in  [pn][outer][Nv][inner] -> out [pn][outer][Dv+1][inner].
 // ------------------------------------------------------------------------------------
-constexpr int kTileElems = 8192;  // 32 KB of LDS
+constexpr int kTileElems = 8192;  // at most 32 KB of LDS per block
 
 __global__ __launch_bounds__(kBlock) void intt_kernel(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int pn, int64_t outer,
     int Nv, int logN, int64_t inner, int Dv1, int W, const uint32_t* __restrict__ itw,
     int64_t tw_stride, const PrimeConst* __restrict__ pcs) {
-  __shared__ uint32_t tile[kTileElems];
+  extern __shared__ uint32_t tile[];  // [Nv][W]
   const int64_t lines = outer * inner;
   const int64_t tiles_per_prime = (lines + W - 1) / W;
   const int prime = (int)(blockIdx.x / tiles_per_prime);
@@ -277,23 +282,42 @@ hipError_t launch_expand(const MatPlan& P, const uint32_t* in, uint32_t* out, in
   }
 }
 
+template <int N, int GL>
+hipError_t launch_det_ng(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hipStream_t st) {
+  if (!P.fused) return det_launch<N, GL>((const uint32_t*)(ws + P.off_eval), detv, P.G, P.pn, P.d_pc, st);
+  FusedDetArgs f;
+  f.pre = (const uint32_t*)(ws + P.off_pre);
+  f.detv = detv;
+  f.R = P.G / P.N[0];
+  f.N0 = P.N[0];
+  f.m0 = P.m[0];
+  f.Q = P.fuse_Q;
+  f.S = P.fuse_S;
+  f.tw0 = P.d_tw + P.tw_off[0];
+  f.tw_stride = P.tw_stride;
+  f.pcs = P.d_pc;
+  f.zero = P.d_zero;
+  f.pn = P.pn;
+  return det_fused_launch<N, GL>(f, st);
+}
+
 template <int N>
-hipError_t launch_det_n(const MatPlan& P, const uint32_t* eval, uint32_t* detv, hipStream_t st) {
+hipError_t launch_det_n(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hipStream_t st) {
   switch (P.det_lanes) {
     case 1:
-      if constexpr (N <= 12) return det_launch<N, 1>(eval, detv, P.G, P.pn, P.d_pc, st);
+      if constexpr (N <= 12) return launch_det_ng<N, 1>(P, ws, detv, st);
       break;
     case 2:
-      if constexpr (N >= 2 && N <= 16) return det_launch<N, 2>(eval, detv, P.G, P.pn, P.d_pc, st);
+      if constexpr (N >= 2 && N <= 16) return launch_det_ng<N, 2>(P, ws, detv, st);
       break;
     case 4:
-      if constexpr (N >= 4 && N <= 24) return det_launch<N, 4>(eval, detv, P.G, P.pn, P.d_pc, st);
+      if constexpr (N >= 4 && N <= 24) return launch_det_ng<N, 4>(P, ws, detv, st);
       break;
     case 8:
-      if constexpr (N >= 8) return det_launch<N, 8>(eval, detv, P.G, P.pn, P.d_pc, st);
+      if constexpr (N >= 8) return launch_det_ng<N, 8>(P, ws, detv, st);
       break;
     case 16:
-      if constexpr (N >= 16) return det_launch<N, 16>(eval, detv, P.G, P.pn, P.d_pc, st);
+      if constexpr (N >= 16) return launch_det_ng<N, 16>(P, ws, detv, st);
       break;
     default:
       break;
@@ -302,10 +326,10 @@ hipError_t launch_det_n(const MatPlan& P, const uint32_t* eval, uint32_t* detv, 
 }
 
 template <int... Ns>
-hipError_t dispatch_det(std::integer_sequence<int, Ns...>, const MatPlan& P, const uint32_t* eval,
+hipError_t dispatch_det(std::integer_sequence<int, Ns...>, const MatPlan& P, const uint8_t* ws,
                         uint32_t* detv, hipStream_t st) {
   hipError_t r = hipErrorInvalidValue;
-  ((P.n == Ns + 1 ? (r = launch_det_n<Ns + 1>(P, eval, detv, st), 0) : 0), ...);
+  ((P.n == Ns + 1 ? (r = launch_det_n<Ns + 1>(P, ws, detv, st), 0) : 0), ...);
   return r;
 }
 
@@ -333,7 +357,7 @@ bool det_config_supported(int n, int lanes) {
 hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st) {
   const int64_t count = P.nent * P.T;
   hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(count)), dim3(kBlock), 0, st, coeffs,
-                     (uint32_t*)(ws + P.off_res), count, P.pn, P.d_pc);
+                     (uint32_t*)(ws + P.off_res), count, P.pn, P.n, P.T, P.d_rowdest, P.d_pc);
   return hipGetLastError();
 }
 
@@ -342,7 +366,8 @@ hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
   const uint32_t* in = (const uint32_t*)(ws + P.off_res);
   uint32_t* bufs[2] = {(uint32_t*)(ws + P.off_tmpA), (uint32_t*)(ws + P.off_tmpB)};
   int which = 0;
-  for (int v = P.k - 1; v >= 0; --v) {
+  const int last = P.fused ? 1 : 0;  // the fused kernel evaluates variable 0 itself
+  for (int v = P.k - 1; v >= last; --v) {
     int64_t outer = 1, inner = 1;
     for (int u = 0; u < v; ++u) outer *= P.m[u];
     for (int u = v + 1; u < P.k; ++u) inner *= P.N[u];
@@ -356,8 +381,8 @@ hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
 }
 
 hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st) {
-  return dispatch_det(std::make_integer_sequence<int, kMaxN>{}, P,
-                      (const uint32_t*)(ws + P.off_eval), (uint32_t*)(ws + P.off_detv), st);
+  return dispatch_det(std::make_integer_sequence<int, kMaxN>{}, P, ws,
+                      (uint32_t*)(ws + P.off_detv), st);
 }
 
 hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
@@ -373,10 +398,14 @@ hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
     const int Nv = P.N[v];
     int logN = 0;
     while ((1 << logN) < Nv) ++logN;
-    const int W = kTileElems / Nv;
+    // W lines per block: as many as fit in kTileElems, fewer while that leaves under ~1024
+    // blocks for the pass (W stays a power of two, so it divides inner when inner >= W)
     const int64_t lines = outer * inner;
+    int W = kTileElems / Nv;
+    while (W > 1 && ((lines + W - 1) / W) * P.pn < 1024) W >>= 1;
     const int64_t tiles = (lines + W - 1) / W;
-    hipLaunchKernelGGL(intt_kernel, dim3((unsigned)(tiles * P.pn)), dim3(kBlock), 0, st, in, out,
+    const size_t lds = (size_t)Nv * W * sizeof(uint32_t);
+    hipLaunchKernelGGL(intt_kernel, dim3((unsigned)(tiles * P.pn)), dim3(kBlock), lds, st, in, out,
                        P.pn, outer, Nv, logN, inner, P.D[v] + 1, W, P.d_itw + P.tw_off[v],
                        P.tw_stride, P.d_pc);
     hipError_t err = hipGetLastError();

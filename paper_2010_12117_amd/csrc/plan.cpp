@@ -232,6 +232,40 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   for (uint32_t p : P.primes) big_mul_small(Mb, p);
   P.L = std::max(1, (big_bitlen(Mb) + 31) / 32);
 
+  // Structural pivoting: eliminate the zero pattern symbolically (an entry of the trailing
+  // block becomes nonzero when it was nonzero or both its row's and its column's entries in
+  // the pivot column and row were) and take, whenever the pivot is structurally zero, the
+  // first lower row that is not. The kernels then meet a zero pivot only by accident
+  // (probability about 1/p per step) and their runtime exchanges stay idle.
+  P.row_order.resize(s.n);
+  for (int i = 0; i < s.n; ++i) P.row_order[i] = i;
+  P.det_sign = 1;
+  if (!P.entry_zero.empty()) {
+    std::vector<uint8_t> S(P.nent);
+    for (int64_t e = 0; e < P.nent; ++e) S[e] = P.entry_zero[e] ? 0 : 1;
+    for (int k = 0; k + 1 < s.n; ++k) {
+      if (!S[k * s.n + k]) {
+        int r = -1;
+        for (int i = k + 1; i < s.n; ++i) {
+          if (S[i * s.n + k]) { r = i; break; }
+        }
+        if (r < 0) continue;  // structurally singular column: the kernels find det 0
+        for (int j = 0; j < s.n; ++j) std::swap(S[k * s.n + j], S[r * s.n + j]);
+        std::swap(P.row_order[k], P.row_order[r]);
+        P.det_sign = -P.det_sign;
+      }
+      for (int i = k + 1; i < s.n; ++i) {
+        if (!S[i * s.n + k]) continue;
+        for (int j = k + 1; j < s.n; ++j) S[i * s.n + j] |= S[k * s.n + j];
+      }
+    }
+    std::vector<uint8_t> z(P.nent);
+    for (int i = 0; i < s.n; ++i) {
+      for (int j = 0; j < s.n; ++j) z[i * s.n + j] = P.entry_zero[P.row_order[i] * s.n + j];
+    }
+    P.entry_zero.swap(z);
+  }
+
   P.pc.resize(P.pn);
   for (int i = 0; i < P.pn; ++i) {
     const uint32_t p = P.primes[i];
@@ -243,7 +277,8 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     c.r1 = (uint32_t)((1ull << 32) % p);
     c.r2 = (uint32_t)mulmod64(c.r1, c.r1, p);
     c.r3 = (uint32_t)mulmod64(c.r2, c.r1, p);
-    c.scale = powmod((uint32_t)(P.G % p), p - 2, p);
+    c.scale = powmod((uint32_t)(P.G % p), p - 2, p);  // 1/G, times the row-order sign
+    if (P.det_sign < 0) c.scale = c.scale ? p - c.scale : 0u;
     P.pc[i] = c;
   }
 
@@ -275,7 +310,37 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   }
   P.off_tmpA = take(pn * P.nent * inter * 4);
   P.off_tmpB = take(pn * P.nent * inter * 4);
-  P.off_eval = s.k == 0 ? P.off_res : take(pn * P.nent * P.G * 4);
+  // Fused evaluation of the first variable inside the elimination kernel: a block stages
+  // Q points of every entry (m0 coefficients each) in LDS, at most kFuseLds bytes, and
+  // handles S values of the first variable's grid index.
+  P.fused = s.k >= 1 && !(flags & 1u);
+  if (P.fused) {
+    constexpr size_t kFuseLds = 64 * 1024;
+    const int64_t R = P.G / P.N[0];
+    const int per_block = 256 / P.det_lanes;
+    int Q = 16;
+    while (Q > 1 && (Q > per_block || Q > R ||
+                     (size_t)(P.nent | 1) * P.m[0] * Q * 4 > kFuseLds)) Q >>= 1;
+    if ((size_t)(P.nent | 1) * P.m[0] * Q * 4 > kFuseLds) {
+      P.fused = false;  // the tile does not fit: evaluate in full, then eliminate
+    } else {
+      const int J = per_block / Q;
+      const int64_t base_blocks = (int64_t)P.pn * ((R + Q - 1) / Q);
+      // enough blocks to fill 256 CUs several times; each block reuses its tile S / J times
+      int iters = (int)std::max<int64_t>(1, (int64_t)P.N[0] * base_blocks / (2048LL * J));
+      iters = std::min(iters, std::max(1, (P.N[0] + J - 1) / J));
+      P.fuse_Q = Q;
+      P.fuse_S = J * iters;
+    }
+  }
+  if (P.fused) {
+    // the pre-tensor is the output of the evaluation pass over variable 1 (pass index
+    // k - 2 counting from the last variable; passes alternate tmpA, tmpB), or the residues
+    P.off_pre = s.k == 1 ? P.off_res : ((s.k - 2) % 2 == 0 ? P.off_tmpA : P.off_tmpB);
+    P.off_eval = SIZE_MAX;
+  } else {
+    P.off_eval = s.k == 0 ? P.off_res : take(pn * P.nent * P.G * 4);
+  }
   P.off_detv = take(pn * P.G * 4);
   // interpolation passes run over the first variable first, trimming N_v to D_v + 1
   size_t iinter = 0;
@@ -300,7 +365,7 @@ int upload_tables(Plan* plan) {
   std::vector<size_t> offs;
   size_t total = 0;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  struct Sizes { size_t pc, tw, gw, gc, ml, zero; };
+  struct Sizes { size_t pc, tw, gw, gc, ml, zero, rd; };
   std::vector<Sizes> sz;
   for (auto& P : plan->mats) {
     int64_t stride = 0;
@@ -316,9 +381,10 @@ int upload_tables(Plan* plan) {
     z.gc = al(4 * P.pn);
     z.ml = al(4 * P.L);
     z.zero = P.entry_zero.empty() ? 0 : al(P.nent);
+    z.rd = al(4 * P.n);
     sz.push_back(z);
     offs.push_back(total);
-    total += z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero;
+    total += z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero + z.rd;
   }
   std::vector<uint8_t> host(std::max<size_t>(total, 256), 0);
   for (size_t idx = 0; idx < plan->mats.size(); ++idx) {
@@ -370,6 +436,8 @@ int upload_tables(Plan* plan) {
     if (z.zero) {
       std::memcpy(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml, P.entry_zero.data(), P.nent);
     }
+    int32_t* rd = (int32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero);
+    for (int i = 0; i < P.n; ++i) rd[P.row_order[i]] = i;
   }
   void* d = nullptr;
   hipError_t err = hipMalloc(&d, host.size());
@@ -392,6 +460,7 @@ int upload_tables(Plan* plan) {
     P.d_mlimbs = (const uint32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc);
     P.d_hlimbs = (const uint32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + z.ml);
     P.d_zero = z.zero ? (const uint8_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml) : nullptr;
+    P.d_rowdest = (const int32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero);
   }
   return 0;
 }

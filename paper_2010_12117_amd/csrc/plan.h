@@ -32,6 +32,11 @@ struct MatPlan {
   std::vector<uint32_t> primes;
   std::vector<PrimeConst> pc;
   std::vector<uint8_t> entry_zero;  // empty when the plan was built without coefficients
+  // Rows in elimination order: row i of the matrix the kernels see is input row
+  // row_order[i]. Chosen on the host from the zero pattern so that no pivot is structurally
+  // zero; det_sign is the sign of that permutation.
+  std::vector<int> row_order;
+  int det_sign = 1;
   double log2_bound_sq = 0;         // upper estimate of log2(B^2)
 
   // device tables (inside the plan's single device allocation)
@@ -44,7 +49,13 @@ struct MatPlan {
   const uint32_t* d_gc = nullptr;    // [pn] (p_0..p_{i-1})^{-1} mod p_i (Montgomery)
   const uint32_t* d_mlimbs = nullptr;  // [L] M = p_0..p_{pn-1}
   const uint32_t* d_hlimbs = nullptr;  // [L] (M-1)/2
-  const uint8_t* d_zero = nullptr;     // [nent] or null
+  const uint8_t* d_zero = nullptr;     // [nent] or null (in elimination row order)
+  const int32_t* d_rowdest = nullptr;  // [n] position of input row i in elimination order
+
+  // fused first-variable evaluation + elimination (det_fused_kernel)
+  bool fused = false;
+  int fuse_Q = 1, fuse_S = 1;
+  size_t off_pre = 0;  // [pn][n*n][m0][R] input of the fused kernel
 
   // workspace layout (bytes, 256-aligned)
   size_t off_res = 0, off_tmpA = 0, off_tmpB = 0, off_eval = 0, off_detv = 0, off_coef = 0,

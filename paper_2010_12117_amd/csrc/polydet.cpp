@@ -207,6 +207,8 @@ polydet_status polydet_plan_query(polydet_plan_t plan, int32_t index, polydet_pl
   out->pn = P.pn;
   out->limbs = P.L;
   out->det_lanes = P.det_lanes;
+  out->det_sign = P.det_sign;
+  for (int i = 0; i < P.n && i < 32; ++i) out->row_order[i] = (uint8_t)P.row_order[i];
   out->in_bytes = P.in_bytes;
   out->out_bytes = P.out_bytes;
   out->workspace_bytes = plan->plan.batch ? plan->plan.ws_bytes : P.ws_bytes;

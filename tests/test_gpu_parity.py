@@ -167,7 +167,9 @@ def test_stages_against_oracle_steps():
     # S2 values at every node, S3 determinants at every node, S4 coefficients mod p
     import torch
     arr = W.random_matrix(np.random.default_rng(9), 3, (2, 1), -40, 40, zero_prob=0.2)
-    got, pl, ws = gpu_solve(arr, flags=pdm.FORCE_PN(2))
+    arr[0, 0] = 0  # a structurally zero pivot: the plan reorders the rows
+    got, pl, ws = gpu_solve(arr, flags=pdm.FORCE_PN(2) | pdm.UNFUSED_EVAL)
+    assert pl.info["row_order"][0] != 0 and pl.info["det_sign"] == -1
     info = pl.info
     n, k = 3, 2
     N = info["N"]
@@ -182,6 +184,8 @@ def test_stages_against_oracle_steps():
     M = P.matrix_from_array(arr, n, k)
     exact = oracle_poly(arr)
     box = tuple(d + 1 for d in info["D"])
+    order = info["row_order"]
+    assert sorted(order) == list(range(n))
     for q, p in enumerate(info["primes"]):
         omegas = [PL.root_of_unity(p, x) for x in N]
         for j in itertools.product(*[range(x) for x in N]):
@@ -189,12 +193,35 @@ def test_stages_against_oracle_steps():
             A = [[OM.evaluate_at_node(M[r][c], p, omegas, j) for c in range(n)] for r in range(n)]
             for r in range(n):
                 for c in range(n):
-                    assert mont_to_plain(ev[q, r * n + c, idx], p) == A[r][c]
-            assert mont_to_plain(dv[q, idx], p) == OM.det_mod(A, p)
+                    # row r of the eliminated matrix is input row order[r]
+                    assert mont_to_plain(ev[q, r * n + c, idx], p) == A[order[r]][c]
+            assert mont_to_plain(dv[q, idx], p) == info["det_sign"] * OM.det_mod(A, p) % p
         for e in itertools.product(*[range(b) for b in box]):
             ci = node_index(e, box)
-            # the interpolation leaves the factor G for the reconstruction
-            assert mont_to_plain(cf[q, ci], p) == exact.get(e, 0) * G % p
+            # the interpolation leaves the factor G (and the row-order sign) for the
+            # reconstruction
+            assert mont_to_plain(cf[q, ci], p) == info["det_sign"] * exact.get(e, 0) * G % p
+
+
+FUSE_CASES = [(3, (2, 1), 1), (12, (3, 3, 3), 1), (13, (1, 2), 2), (22, (2, 1), 4),
+              (17, (1, 1, 1), 8), (30, (1, 2), 16), (9, (4,), 1), (5, (2, 0, 1), 2)]
+
+
+@pytest.mark.parametrize("n,deg,lanes", FUSE_CASES)
+def test_fused_matches_unfused_and_stage_values(n, deg, lanes):
+    # the fused first-variable evaluation gives the same determinant at every grid point as
+    # the full evaluation tensor, including padded columns of the last lane slot
+    rng = np.random.default_rng(300 + n)
+    arr = W.random_matrix(rng, n, deg, -99, 99, zero_prob=0.3)
+    log2 = {1: 0, 2: 1, 4: 2, 8: 3, 16: 4}[lanes]
+    a, pla, wsa = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2))
+    b, plb, wsb = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2) | pdm.UNFUSED_EVAL)
+    assert box_to_dict(a) == box_to_dict(b)
+    ia, ib = pla.info, plb.info
+    nb = 4 * ia["pn"] * ia["G"]
+    da = wsa.cpu().numpy()[ia["off_detv"]:ia["off_detv"] + nb]
+    db = wsb.cpu().numpy()[ib["off_detv"]:ib["off_detv"] + nb]
+    assert np.array_equal(da, db)
 
 
 def test_config2_bit_exact(pool):

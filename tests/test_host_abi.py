@@ -160,3 +160,26 @@ def test_limb_decoding():
         rows.append([(u >> (32 * l)) & 0xFFFFFFFF for l in range(L)])
     arr = np.array(rows, dtype=np.uint32)
     assert B.limbs_to_ints(arr) == vals
+
+
+def test_structural_row_order():
+    # the plan reorders rows so that symbolic elimination of the zero pattern meets no
+    # structurally zero pivot; det_sign is the permutation's sign
+    for arr in [W.config2(), W.config3a(), W.config3b()[0]] + W.config4(count=8):
+        n, deg = B.shape_of(arr)
+        info = pdm.plan(n, deg, host_coeffs=arr, flags=pdm.HOST_ONLY).info
+        order = list(info["row_order"])
+        assert sorted(order) == list(range(n))
+        inv = sum(1 for i in range(n) for j in range(i + 1, n) if order[i] > order[j])
+        assert info["det_sign"] == (-1) ** inv
+        S = (np.abs(arr).reshape(n * n, -1).sum(axis=1) != 0).reshape(n, n)[order]
+        S = S.copy()
+        for k in range(n - 1):
+            if S[k:, k].any():
+                assert S[k, k]
+            for i in range(k + 1, n):
+                if S[i, k]:
+                    S[i, k + 1:] |= S[k, k + 1:]
+    # without coefficients the order is the identity
+    info = pdm.plan(5, (1,), coeff_bits=3, flags=pdm.HOST_ONLY).info
+    assert info["row_order"] == tuple(range(5)) and info["det_sign"] == 1
