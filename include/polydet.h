@@ -74,6 +74,14 @@ typedef struct polydet_shape {
  * first variable is fused into the elimination kernel and that tensor is never written
  * (off_eval is then SIZE_MAX). Results are identical either way. */
 #define POLYDET_UNFUSED_EVAL ((uint32_t)1u)
+/* POLYDET_BATCH_PLAIN (batch plans): solve the matrices one after another with the
+ * single-matrix launches, instead of the default batched launches (matrices grouped into
+ * chunks that fit the workspace; per chunk one persistent launch per stage and one per
+ * matrix order for the elimination). Results are identical either way. */
+#define POLYDET_BATCH_PLAIN ((uint32_t)2u)
+/* The workspace budget of one chunk of a batched solve is 16 GiB, or the value of the
+ * environment variable POLYDET_BATCH_BUDGET_MB (in MiB) read when the plan is made; a single
+ * matrix larger than the budget forms a chunk of its own. */
 /* Plan flags. POLYDET_FORCE_PN(x): use exactly x primes (x >= the number the bound needs,
  * else EINVAL). POLYDET_PRIME_OFFSET(x): skip the first x primes of the table (a disjoint
  * prime set; the result does not depend on it). */
@@ -161,7 +169,9 @@ polydet_status polydet_solve(polydet_plan_t plan, const int64_t* d_coeffs, uint3
  * d_coeffs: device int64 buffer holding every matrix's coefficients; coeff_offsets[i]
  * (host, in int64 elements) is where matrix i starts. d_out: device uint32 buffer;
  * out_offsets[i] (host, in uint32 elements) is where matrix i's limbs start. Outputs of
- * different matrices must not overlap. */
+ * different matrices must not overlap. The offsets are copied to the device on the stream
+ * when they differ from the previous call's; with unchanged offsets the solve only enqueues
+ * kernels (it can be captured in a HIP graph). Solves of one batch plan must not overlap. */
 polydet_status polydet_solve_batch(polydet_plan_t plan, const int64_t* d_coeffs,
                                    const int64_t* coeff_offsets, uint32_t* d_out,
                                    const int64_t* out_offsets, void* d_workspace,

@@ -33,6 +33,7 @@ def PRIME_OFFSET(x: int) -> int:
 
 
 UNFUSED_EVAL = 1
+BATCH_PLAIN = 2
 HOST_ONLY = 1 << 31
 STAGE_TIMING = 1 << 30
 STAGES = ("reduce", "evaluate", "determinants", "interpolate", "reconstruct")
@@ -268,6 +269,8 @@ def solve_batch_device(pl: Plan, d_coeffs, coeff_offsets: Sequence[int], d_out,
     if workspace is None:
         workspace = torch.empty(pl.infos[0]["workspace_bytes"], dtype=torch.uint8,
                                 device=d_coeffs.device)
+    if d_coeffs.dtype != torch.int64 or not d_coeffs.is_cuda or d_out.dtype != torch.int32:
+        raise ValueError("coefficients must be int64 and outputs int32 device tensors")
     co = np.ascontiguousarray(coeff_offsets, dtype=np.int64)
     oo = np.ascontiguousarray(out_offsets, dtype=np.int64)
     P64 = ctypes.POINTER(ctypes.c_int64)

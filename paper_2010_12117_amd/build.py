@@ -36,6 +36,7 @@ def _units():
     units = [
         ("plan.o", os.path.join(CSRC, "plan.cpp"), []),
         ("polydet.o", os.path.join(CSRC, "polydet.cpp"), []),
+        ("batch_plan.o", os.path.join(CSRC, "batch_plan.cpp"), []),
         ("kernels.o", os.path.join(CSRC, "kernels.hip"), []),
     ]
     for part in range(DET_PARTS):

@@ -1,0 +1,310 @@
+// Host side of the batched solve (batch.h): chunking of the matrices by workspace budget,
+// per-chunk workspace layout, the list of launches and their descriptor tables.
+#include "batch_plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+
+#include "kernels.h"
+
+namespace pd {
+
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace regions of one matrix inside a chunk (relative to the chunk's base). The fused
+// path needs the residues, the evaluation passes before the first variable, the
+// determinants, the interpolation ping-pong and the coefficients.
+struct Regions {
+  size_t res, tmpA, tmpB, pre, detv, iA, iB, coef, bytes;
+};
+
+Regions regions_of(const MatPlan& P, size_t base) {
+  Regions r{};
+  size_t off = base;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = al256(off + bytes);
+    return o;
+  };
+  const size_t pn = P.pn;
+  r.res = take(pn * P.nent * P.T * 4);
+  size_t inter = 0;
+  for (int v = P.k - 1; v >= 1; --v) {
+    int64_t sz = 1;
+    for (int u = 0; u < v; ++u) sz *= P.m[u];
+    for (int u = v; u < P.k; ++u) sz *= P.N[u];
+    inter = std::max(inter, (size_t)sz);
+  }
+  r.tmpA = take(pn * P.nent * inter * 4);
+  r.tmpB = take(pn * P.nent * inter * 4);
+  r.pre = P.k == 1 ? r.res : ((P.k - 2) % 2 == 0 ? r.tmpA : r.tmpB);
+  r.detv = take(pn * P.G * 4);
+  size_t iinter = 0;
+  for (int v = 0; v + 1 < P.k; ++v) {
+    int64_t sz = 1;
+    for (int u = 0; u <= v; ++u) sz *= P.D[u] + 1;
+    for (int u = v + 1; u < P.k; ++u) sz *= P.N[u];
+    iinter = std::max(iinter, (size_t)sz);
+  }
+  r.iA = take(pn * iinter * 4);
+  r.iB = take(pn * iinter * 4);
+  r.coef = take(pn * P.C * 4);
+  r.bytes = off - base;
+  return r;
+}
+
+}  // namespace
+
+bool batchable(const MatPlan& P) {
+  if (!P.fused || P.k < 1) return false;
+  for (int v = 1; v < P.k; ++v) {
+    if (P.m[v] > kBatchMaxM) return false;
+  }
+  return true;
+}
+
+size_t batch_footprint(const MatPlan& P) { return regions_of(P, 0).bytes; }
+
+std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPlan* out) {
+  BatchPlan B;
+  // order: batchable matrices grouped by order n (fewer elimination launches per chunk),
+  // largest grids first within an order; the rest are solved one by one
+  std::vector<int> order;
+  for (int i = 0; i < (int)mats.size(); ++i) {
+    if (batchable(mats[i])) order.push_back(i); else B.singles.push_back(i);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (mats[a].n != mats[b].n) return mats[a].n > mats[b].n;
+    return mats[a].G * mats[a].pn > mats[b].G * mats[b].pn;
+  });
+  // greedy chunks under the budget
+  std::vector<std::vector<int>> chunks;
+  size_t used = 0;
+  for (int i : order) {
+    const size_t f = al256(batch_footprint(mats[i]));
+    if (chunks.empty() || used + f > budget) {
+      chunks.emplace_back();
+      used = 0;
+    }
+    chunks.back().push_back(i);
+    used += f;
+  }
+  size_t ws_need = 0;
+  for (int i : B.singles) ws_need = std::max(ws_need, mats[i].ws_bytes);
+
+  std::vector<uint8_t> blob;
+  auto push = [&](const void* p, size_t bytes) {
+    const size_t off = al256(blob.size());
+    blob.resize(off + bytes);
+    std::memcpy(blob.data() + off, p, bytes);
+    return off;
+  };
+
+  for (const auto& chunk : chunks) {
+    // layout
+    std::vector<Regions> reg;
+    size_t base = 0;
+    for (int i : chunk) {
+      reg.push_back(regions_of(mats[i], base));
+      base = al256(base + reg.back().bytes);
+    }
+    ws_need = std::max(ws_need, base);
+
+    // S1 reduce: one launch
+    {
+      std::vector<BReduce> d;
+      int64_t vb = 0;
+      for (size_t c = 0; c < chunk.size(); ++c) {
+        const MatPlan& P = mats[chunk[c]];
+        BReduce r{};
+        r.block0 = vb;
+        r.count = P.nent * P.T;
+        r.T = P.T;
+        r.res_off = (int64_t)reg[c].res;
+        r.mat = chunk[c];
+        r.n = P.n;
+        r.pn = P.pn;
+        r.pc = P.d_pc;
+        r.rowdest = P.d_rowdest;
+        d.push_back(r);
+        vb += (r.count + 255) / 256;
+      }
+      BLaunch L{};
+      L.kind = BLaunch::kReduce;
+      L.desc_off = push(d.data(), d.size() * sizeof(BReduce));
+      L.ndesc = (int)d.size();
+      L.vblocks = vb;
+      B.launches.push_back(L);
+    }
+    // S2 evaluation passes (last variable first), stopping before the first variable;
+    // pass s covers the matrices with at least s + 2 variables
+    int maxk = 0;
+    for (int i : chunk) maxk = std::max(maxk, mats[i].k);
+    for (int s = 0; s + 1 < maxk; ++s) {
+      std::vector<BExpand> d;
+      int64_t vb = 0;
+      for (size_t c = 0; c < chunk.size(); ++c) {
+        const MatPlan& P = mats[chunk[c]];
+        const int v = P.k - 1 - s;
+        if (v < 1) continue;
+        int64_t outer = 1, inner = 1;
+        for (int u = 0; u < v; ++u) outer *= P.m[u];
+        for (int u = v + 1; u < P.k; ++u) inner *= P.N[u];
+        const size_t in_off = s == 0 ? reg[c].res : (s % 2 == 1 ? reg[c].tmpA : reg[c].tmpB);
+        const size_t out_off = s % 2 == 0 ? reg[c].tmpA : reg[c].tmpB;
+        BExpand e{};
+        e.block0 = vb;
+        e.in_off = (int64_t)in_off;
+        e.out_off = (int64_t)out_off;
+        e.B = (int64_t)P.pn * P.nent;
+        e.outer = outer;
+        e.inner = inner;
+        e.nent = P.nent;
+        e.tw_stride = P.tw_stride;
+        e.m = P.m[v];
+        e.Nv = P.N[v];
+        e.JC = expand_outputs_per_thread(P.N[v], inner);
+        e.tw = P.d_tw + P.tw_off[v];
+        e.pc = P.d_pc;
+        e.zero = P.d_zero;
+        d.push_back(e);
+        vb += (e.B * outer * (e.Nv / e.JC) * inner + 255) / 256;
+      }
+      if (d.empty()) continue;
+      BLaunch L{};
+      L.kind = BLaunch::kExpand;
+      L.desc_off = push(d.data(), d.size() * sizeof(BExpand));
+      L.ndesc = (int)d.size();
+      L.vblocks = vb;
+      B.launches.push_back(L);
+    }
+    // S3 elimination with the first variable's evaluation: one launch per (order, lanes)
+    std::map<std::pair<int, int>, std::vector<size_t>> classes;
+    for (size_t c = 0; c < chunk.size(); ++c) {
+      const MatPlan& P = mats[chunk[c]];
+      classes[{-P.n, P.det_lanes}].push_back(c);
+    }
+    for (auto& kv : classes) {
+      std::vector<BDet> d;
+      int64_t vb = 0;
+      size_t lds = 0;
+      for (size_t c : kv.second) {
+        const MatPlan& P = mats[chunk[c]];
+        BDet e{};
+        e.block0 = vb;
+        e.pre_off = (int64_t)reg[c].pre;
+        e.detv_off = (int64_t)reg[c].detv;
+        e.R = P.G / P.N[0];
+        e.tw_stride = P.tw_stride;
+        e.rtiles = (e.R + P.fuse_Q - 1) / P.fuse_Q;
+        e.jtiles = (P.N[0] + P.fuse_S - 1) / P.fuse_S;
+        e.N0 = P.N[0];
+        e.m0 = P.m[0];
+        e.Q = P.fuse_Q;
+        e.S = P.fuse_S;
+        e.tw0 = P.d_tw + P.tw_off[0];
+        e.pc = P.d_pc;
+        e.zero = P.d_zero;
+        d.push_back(e);
+        vb += (int64_t)P.pn * e.rtiles * e.jtiles;
+        lds = std::max(lds, (size_t)(P.nent | 1) * P.m[0] * P.fuse_Q * 4);
+      }
+      BLaunch L{};
+      L.kind = BLaunch::kDet;
+      L.desc_off = push(d.data(), d.size() * sizeof(BDet));
+      L.ndesc = (int)d.size();
+      L.vblocks = vb;
+      L.n = -kv.first.first;
+      L.lanes = kv.first.second;
+      L.lds = lds;
+      B.launches.push_back(L);
+    }
+    // S4 interpolation passes: pass v covers the matrices with more than v variables
+    for (int v = 0; v < maxk; ++v) {
+      std::vector<BIntt> d;
+      int64_t vb = 0;
+      size_t lds = 0;
+      for (size_t c = 0; c < chunk.size(); ++c) {
+        const MatPlan& P = mats[chunk[c]];
+        if (v >= P.k) continue;
+        int64_t outer = 1, inner = 1;
+        for (int u = 0; u < v; ++u) outer *= P.D[u] + 1;
+        for (int u = v + 1; u < P.k; ++u) inner *= P.N[u];
+        const size_t in_off = v == 0 ? reg[c].detv : (v % 2 == 1 ? reg[c].iA : reg[c].iB);
+        const size_t out_off = v == P.k - 1 ? reg[c].coef : (v % 2 == 0 ? reg[c].iA : reg[c].iB);
+        const int Nv = P.N[v];
+        int logN = 0;
+        while ((1 << logN) < Nv) ++logN;
+        const int64_t lines = outer * inner;
+        const int W = intt_lines_per_block(lines, Nv, P.pn);
+        BIntt e{};
+        e.block0 = vb;
+        e.in_off = (int64_t)in_off;
+        e.out_off = (int64_t)out_off;
+        e.outer = outer;
+        e.inner = inner;
+        e.tw_stride = P.tw_stride;
+        e.tiles = (lines + W - 1) / W;
+        e.pn = P.pn;
+        e.Nv = Nv;
+        e.logN = logN;
+        e.Dv1 = P.D[v] + 1;
+        e.W = W;
+        e.itw = P.d_itw + P.tw_off[v];
+        e.pc = P.d_pc;
+        d.push_back(e);
+        vb += e.tiles * P.pn;
+        lds = std::max(lds, (size_t)Nv * W * 4);
+      }
+      if (d.empty()) continue;
+      BLaunch L{};
+      L.kind = BLaunch::kIntt;
+      L.desc_off = push(d.data(), d.size() * sizeof(BIntt));
+      L.ndesc = (int)d.size();
+      L.vblocks = vb;
+      L.lds = lds;
+      B.launches.push_back(L);
+    }
+    // S5 reconstruction: one launch
+    {
+      std::vector<BGarner> d;
+      int64_t vb = 0;
+      int pnmax = 1;
+      for (size_t c = 0; c < chunk.size(); ++c) {
+        const MatPlan& P = mats[chunk[c]];
+        BGarner g{};
+        g.block0 = vb;
+        g.coef_off = (int64_t)reg[c].coef;
+        g.C = P.C;
+        g.mat = chunk[c];
+        g.pn = P.pn;
+        g.L = P.L;
+        g.pc = P.d_pc;
+        g.gw = P.d_gw;
+        g.gc = P.d_gc;
+        g.ml = P.d_mlimbs;
+        g.hl = P.d_hlimbs;
+        d.push_back(g);
+        vb += (P.C + 255) / 256;
+        pnmax = std::max(pnmax, P.pn);
+      }
+      BLaunch L{};
+      L.kind = BLaunch::kGarner;
+      L.desc_off = push(d.data(), d.size() * sizeof(BGarner));
+      L.ndesc = (int)d.size();
+      L.vblocks = vb;
+      L.pnmax = pnmax;
+      B.launches.push_back(L);
+    }
+  }
+  B.desc_blob = std::move(blob);
+  B.chunks = (int)chunks.size();
+  B.ws_bytes = std::max<size_t>(ws_need, 256);
+  *out = std::move(B);
+  return "";
+}
+
+}  // namespace pd

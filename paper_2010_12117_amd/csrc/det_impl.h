@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "batch.h"
 #include "det.h"
 #include "modarith.h"
 
@@ -133,20 +134,19 @@ __global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restri
 // offset) and then, for S values of j0, each lane group rebuilds its matrix at the point
 // (j0, r0 + q) by Horner's rule in w0^j0 (the evaluation of Section 2 along x1) and
 // eliminates it. Point index = j0 R + r.
+// One block's share of the fused kernel: prime `prime`, tile `bx` = (j-range, r-range).
 template <int N, int GL>
-__global__ __launch_bounds__(kDetBlock) void det_fused_kernel(
-    const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, int64_t R, int N0, int m0,
-    int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
+__device__ __forceinline__ void det_fused_body(
+    uint32_t* tile, const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, int64_t R,
+    int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, int prime, int64_t bx) {
   constexpr int C = (N + GL - 1) / GL;
   constexpr int NE = N * N;
   constexpr int NEP = NE | 1;
-  extern __shared__ uint32_t tile[];  // [m0][Q][NEP]
-  const int prime = blockIdx.y;
   const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
   const int64_t rtiles = (R + Q - 1) / Q;
-  const int64_t r0 = (blockIdx.x % rtiles) * Q;
-  const int jbase = (int)(blockIdx.x / rtiles) * S;
+  const int64_t r0 = (bx % rtiles) * Q;
+  const int jbase = (int)(bx / rtiles) * S;
   const uint32_t* src = pre + (int64_t)prime * NE * m0 * R;
 
   const int mq = m0 * Q;
@@ -235,12 +235,49 @@ __global__ __launch_bounds__(kDetBlock) void det_fused_kernel(
 }
 
 template <int N, int GL>
+__global__ __launch_bounds__(kDetBlock) void det_fused_kernel(
+    const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, int64_t R, int N0, int m0,
+    int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
+  extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
+  det_fused_body<N, GL>(tile, pre, detv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero, blockIdx.y,
+                        blockIdx.x);
+}
+
+// Batched form: blocks walk the virtual blocks of every matrix of this order in the launch;
+// virtual block vb of matrix d is (prime, tile) = divmod(vb - block0, rtiles * jtiles).
+template <int N, int GL>
+__global__ __launch_bounds__(kDetBlock) void det_fused_batch_kernel(
+    const BDet* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws) {
+  extern __shared__ uint32_t tile[];
+  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
+    const BDet& d = desc[find_desc(desc, ndesc, vb)];
+    const int64_t local = vb - d.block0;
+    const int64_t per_prime = d.rtiles * d.jtiles;
+    const int prime = (int)(local / per_prime);
+    det_fused_body<N, GL>(tile, (const uint32_t*)(ws + d.pre_off), (uint32_t*)(ws + d.detv_off),
+                          d.R, d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride, d.pc, d.zero, prime,
+                          local - (int64_t)prime * per_prime);
+    __syncthreads();  // the next virtual block refills the tile
+  }
+}
+
+template <int N, int GL>
 hipError_t det_launch(const uint32_t* eval, uint32_t* detv, int64_t npts, int pn,
                       const PrimeConst* pcs, hipStream_t st) {
   constexpr int per_block = kDetBlock / GL;
   const int64_t bx = (npts + per_block - 1) / per_block;
   hipLaunchKernelGGL((det_kernel<N, GL>), dim3((unsigned)bx, (unsigned)pn), dim3(kDetBlock), 0, st,
                      eval, detv, npts, pcs);
+  return hipGetLastError();
+}
+
+template <int N, int GL>
+hipError_t det_fused_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
+                                  uint8_t* ws, hipStream_t st) {
+  const int64_t grid = vblocks < kPersistentBlocks ? vblocks : kPersistentBlocks;
+  hipLaunchKernelGGL((det_fused_batch_kernel<N, GL>), dim3((unsigned)(grid < 1 ? 1 : grid)),
+                     dim3(kDetBlock), lds, st, desc, ndesc, vblocks, ws);
   return hipGetLastError();
 }
 

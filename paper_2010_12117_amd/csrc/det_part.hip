@@ -11,7 +11,9 @@ namespace pd {
 #define PD_DET(N, GL)                                                                  \
   template hipError_t det_launch<N, GL>(const uint32_t*, uint32_t*, int64_t, int,     \
                                         const PrimeConst*, hipStream_t);              \
-  template hipError_t det_fused_launch<N, GL>(const FusedDetArgs&, hipStream_t);
+  template hipError_t det_fused_launch<N, GL>(const FusedDetArgs&, hipStream_t);          \
+  template hipError_t det_fused_batch_launch<N, GL>(const BDet*, int, int64_t, size_t,    \
+                                                    uint8_t*, hipStream_t);
 
 #if DET_PART == 0
 PD_DET(1, 1) PD_DET(2, 1) PD_DET(3, 1) PD_DET(4, 1) PD_DET(5, 1) PD_DET(6, 1)

@@ -1,13 +1,16 @@
 // HIP kernels for gfx950 of the modular determinant (Wei & Chen, arXiv 2010.12117,
 // Algorithm 1): reduction of the integer coefficients, evaluation on the grid of roots of
-// unity (the FFT stage), one determinant per (prime, grid point) (the DET stage),
-// interpolation (the IFFT stage) and mixed-radix reconstruction (the CRT stage).
+// unity (the FFT stage), interpolation (the IFFT stage) and mixed-radix reconstruction (the
+// CRT stage); the elimination (the DET stage) is in det_impl.h.
 //
+// Each stage is a device-side body shared by a single-matrix kernel (parameters as kernel
+// arguments) and a batched kernel (parameters from a per-matrix descriptor table, batch.h).
 // Every value below is a Montgomery representative (modarith.h) until the reconstruction.
 #include <hip/hip_runtime.h>
 
 #include <utility>
 
+#include "batch.h"
 #include "det.h"
 #include "kernels.h"
 #include "modarith.h"
@@ -23,18 +26,20 @@ inline unsigned blocks_for(int64_t work, int per_block = kBlock) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
+inline unsigned persistent_grid(int64_t vblocks) {
+  return (unsigned)(vblocks < kPersistentBlocks ? (vblocks < 1 ? 1 : vblocks) : kPersistentBlocks);
+}
+
 // ------------------------------------------------------------------------------------
 // S1: int64 coefficient -> representative of (c mod p) for every prime.
 // |c| = hi 2^32 + lo with hi <= 2^31, so c~ = mm(hi, R^3) + mm(lo, R^2), negated for c < 0.
-// ------------------------------------------------------------------------------------
 // Entries are written in elimination row order: input row r goes to row rowdest[r].
-__global__ __launch_bounds__(kBlock) void reduce_kernel(const int64_t* __restrict__ in,
-                                                        uint32_t* __restrict__ out,
-                                                        int64_t count, int pn, int n, int64_t T,
-                                                        const int32_t* __restrict__ rowdest,
-                                                        const PrimeConst* __restrict__ pcs) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= count) return;
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ void reduce_body(const int64_t* __restrict__ in,
+                                            uint32_t* __restrict__ out, int64_t i, int64_t count,
+                                            int pn, int n, int64_t T,
+                                            const int32_t* __restrict__ rowdest,
+                                            const PrimeConst* __restrict__ pcs) {
   const int64_t e = i / T;
   const int row = (int)(e / n), col = (int)(e - (int64_t)row * n);
   const int64_t dst = ((int64_t)rowdest[row] * n + col) * T + (i - e * T);
@@ -50,30 +55,58 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(const int64_t* __restric
   }
 }
 
+__global__ __launch_bounds__(kBlock) void reduce_kernel(const int64_t* __restrict__ in,
+                                                        uint32_t* __restrict__ out,
+                                                        int64_t count, int pn, int n, int64_t T,
+                                                        const int32_t* __restrict__ rowdest,
+                                                        const PrimeConst* __restrict__ pcs) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < count) reduce_body(in, out, i, count, pn, n, T, rowdest, pcs);
+}
+
+__global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
+    const BReduce* __restrict__ desc, int ndesc, int64_t vblocks, const int64_t* __restrict__ coeffs,
+    const int64_t* __restrict__ coeff_offsets, uint8_t* __restrict__ ws) {
+  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
+    const BReduce& d = desc[find_desc(desc, ndesc, vb)];
+    const int64_t i = (vb - d.block0) * kBlock + threadIdx.x;
+    if (i < d.count) {
+      reduce_body(coeffs + coeff_offsets[d.mat], (uint32_t*)(ws + d.res_off), i, d.count, d.pn,
+                  d.n, d.T, d.rowdest, d.pc);
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // S2: evaluation along one variable. For every line (b, o, q) of
 //   in  [B][outer][m][inner]   (coefficients of x_v^e, e < m, other axes as given)
 //   out [B][outer][Nv][inner]  out[j] = sum_e in[e] w_v^{e j}
 // the values at the Nv-th roots of unity (the DFT over Z/pZ of Section 2, restricted to the
 // m nonzero leading coefficients of the zero-padded line). b = prime * nent + entry.
-// Consecutive lanes take consecutive q, so loads and stores are coalesced whenever
-// inner >= 64; the twiddles for a given j are then the same address across the wave.
+// A thread computes JC consecutive outputs j of one line; consecutive lanes take
+// consecutive q (coalesced when inner >= 64) and, for small inner, consecutive j-chunks, so
+// that short lines still spread over many lanes with contiguous stores. M >= m is the
+// register bound on the coefficients; terms e >= m are skipped (a uniform test).
 // ------------------------------------------------------------------------------------
 template <int M>
-__global__ __launch_bounds__(kBlock) void expand_kernel(
-    const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t B, int64_t outer,
-    int m, int Nv, int64_t inner, int64_t nent, const uint32_t* __restrict__ tw,
-    int64_t tw_stride, const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
-  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= B * outer * inner) return;
+__device__ __forceinline__ void expand_body(
+    const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t idx, int64_t B,
+    int64_t outer, int m, int Nv, int JC, int64_t inner, int64_t nent,
+    const uint32_t* __restrict__ tw, int64_t tw_stride, const PrimeConst* __restrict__ pcs,
+    const uint8_t* __restrict__ zero) {
+  const int nJB = Nv / JC;
+  if (idx >= B * outer * nJB * inner) return;
   const int64_t q = idx % inner;
-  const int64_t bo = idx / inner;
+  const int64_t r = idx / inner;
+  const int jb = (int)(r % nJB);
+  const int64_t bo = r / nJB;
   const int64_t b = bo / outer;
   const int prime = (int)(b / nent);
   const int64_t entry = b - (int64_t)prime * nent;
   uint32_t* dst = out + bo * Nv * inner + q;
+  const int j0 = jb * JC;
   if (zero && zero[entry]) {
-    for (int j = 0; j < Nv; ++j) dst[(int64_t)j * inner] = 0u;
+    for (int j = j0; j < j0 + JC; ++j) dst[(int64_t)j * inner] = 0u;
     return;
   }
   const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv;
@@ -83,18 +116,41 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
 #pragma unroll
   for (int e = 0; e < M; ++e) x[e] = e < m ? src[(int64_t)e * inner] : 0u;
   const int mask = Nv - 1;
-  for (int j = 0; j < Nv; ++j) {
+  for (int j = j0; j < j0 + JC; ++j) {
     uint32_t acc = x[0];
 #pragma unroll
     for (int e = 1; e < M; e += 2) {
-      if (e + 1 < M) {
-        acc = addm(acc,
-                   mm2(x[e], w[(e * j) & mask], x[e + 1], w[((e + 1) * j) & mask], p, pinv), p);
-      } else {
-        acc = addm(acc, mm(x[e], w[(e * j) & mask], p, pinv), p);
+      if (e < m) {
+        if (e + 1 < M) {
+          acc = addm(acc,
+                     mm2(x[e], w[(e * j) & mask], x[e + 1], w[((e + 1) * j) & mask], p, pinv), p);
+        } else {
+          acc = addm(acc, mm(x[e], w[(e * j) & mask], p, pinv), p);
+        }
       }
     }
     dst[(int64_t)j * inner] = acc;
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void expand_kernel(
+    const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t B, int64_t outer,
+    int m, int Nv, int JC, int64_t inner, int64_t nent, const uint32_t* __restrict__ tw,
+    int64_t tw_stride, const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  expand_body<M>(in, out, idx, B, outer, m, Nv, JC, inner, nent, tw, tw_stride, pcs, zero);
+}
+
+__global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __restrict__ desc,
+                                                              int ndesc, int64_t vblocks,
+                                                              uint8_t* __restrict__ ws) {
+  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
+    const BExpand& d = desc[find_desc(desc, ndesc, vb)];
+    const int64_t idx = (vb - d.block0) * kBlock + threadIdx.x;
+    expand_body<kBatchMaxM>((const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), idx,
+                            d.B, d.outer, d.m, d.Nv, d.JC, d.inner, d.nent, d.tw, d.tw_stride,
+                            d.pc, d.zero);
   }
 }
 
@@ -103,19 +159,17 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
 // 1/N factor is applied once in the reconstruction). A block loads a tile of W lines of
 // length Nv into LDS in bit-reversed order, runs log2 Nv radix-2 decimation-in-time stages
 // and writes the first D_v + 1 outputs of each line:
-//   in  [pn][outer][Nv][inner] -> out [pn][outer][Dv+1][inner].
+//   in  [pn][outer][Nv][inner] -> out [pn][outer][Dv1][inner];  tile index = prime * tiles + t.
 // ------------------------------------------------------------------------------------
-constexpr int kTileElems = 8192;  // at most 32 KB of LDS per block
-
-__global__ __launch_bounds__(kBlock) void intt_kernel(
-    const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int pn, int64_t outer,
-    int Nv, int logN, int64_t inner, int Dv1, int W, const uint32_t* __restrict__ itw,
-    int64_t tw_stride, const PrimeConst* __restrict__ pcs) {
-  extern __shared__ uint32_t tile[];  // [Nv][W]
+__device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __restrict__ in,
+                                          uint32_t* __restrict__ out, int64_t block,
+                                          int64_t outer, int Nv, int logN, int64_t inner, int Dv1,
+                                          int W, const uint32_t* __restrict__ itw,
+                                          int64_t tw_stride, const PrimeConst* __restrict__ pcs) {
   const int64_t lines = outer * inner;
   const int64_t tiles_per_prime = (lines + W - 1) / W;
-  const int prime = (int)(blockIdx.x / tiles_per_prime);
-  const int64_t line0 = (blockIdx.x - (int64_t)prime * tiles_per_prime) * W;
+  const int prime = (int)(block / tiles_per_prime);
+  const int64_t line0 = (block - (int64_t)prime * tiles_per_prime) * W;
   const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv;
   const uint32_t* w = itw + (int64_t)prime * tw_stride;
   const uint32_t* src = in + (int64_t)prime * outer * Nv * inner;
@@ -163,6 +217,26 @@ __global__ __launch_bounds__(kBlock) void intt_kernel(
   }
 }
 
+__global__ __launch_bounds__(kBlock) void intt_kernel(
+    const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t outer, int Nv, int logN,
+    int64_t inner, int Dv1, int W, const uint32_t* __restrict__ itw, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs) {
+  extern __shared__ uint32_t tile[];  // [Nv][W]
+  intt_body(tile, in, out, blockIdx.x, outer, Nv, logN, inner, Dv1, W, itw, tw_stride, pcs);
+}
+
+__global__ __launch_bounds__(kBlock) void intt_batch_kernel(const BIntt* __restrict__ desc,
+                                                            int ndesc, int64_t vblocks,
+                                                            uint8_t* __restrict__ ws) {
+  extern __shared__ uint32_t tile[];
+  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
+    const BIntt& d = desc[find_desc(desc, ndesc, vb)];
+    intt_body(tile, (const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), vb - d.block0,
+              d.outer, d.Nv, d.logN, d.inner, d.Dv1, d.W, d.itw, d.tw_stride, d.pc);
+    __syncthreads();  // the next virtual block reuses the tile
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // S5: mixed-radix conversion (Section 3.4, Algorithm 4; one lane per coefficient, as the
 // paper parallelises over coefficients rather than digits). With x_i the residue mod p_i:
@@ -171,40 +245,49 @@ __global__ __launch_bounds__(kBlock) void intt_kernel(
 // then the symmetric range: X - M when X > (M-1)/2, written as L two's-complement limbs.
 // ------------------------------------------------------------------------------------
 template <int PN>
-__global__ __launch_bounds__(kBlock) void garner_kernel(
-    const uint32_t* __restrict__ coef, uint32_t* __restrict__ out, int64_t C, int pn, int L,
-    const PrimeConst* __restrict__ pcs, const uint32_t* __restrict__ gw,
-    const uint32_t* __restrict__ gc, const uint32_t* __restrict__ mlimbs,
-    const uint32_t* __restrict__ hlimbs) {
-  __shared__ uint32_t s_gw[PN * PN];
-  __shared__ uint32_t s_p[PN], s_pinv[PN], s_gc[PN], s_scale[PN], s_m[PN], s_h[PN];
-  for (int i = threadIdx.x; i < pn * pn; i += kBlock) s_gw[(i / pn) * PN + i % pn] = gw[i];
+struct GarnerShared {
+  uint32_t gw[PN * PN];
+  uint32_t p[PN], pinv[PN], gc[PN], scale[PN], m[PN], h[PN];
+};
+
+template <int PN>
+__device__ __forceinline__ void garner_load(GarnerShared<PN>& s, int pn, int L,
+                                            const PrimeConst* __restrict__ pcs,
+                                            const uint32_t* __restrict__ gw,
+                                            const uint32_t* __restrict__ gc,
+                                            const uint32_t* __restrict__ mlimbs,
+                                            const uint32_t* __restrict__ hlimbs) {
+  for (int i = threadIdx.x; i < pn * pn; i += kBlock) s.gw[(i / pn) * PN + i % pn] = gw[i];
   for (int i = threadIdx.x; i < pn; i += kBlock) {
-    s_p[i] = pcs[i].p;
-    s_pinv[i] = pcs[i].pinv;
-    s_gc[i] = gc[i];
-    s_scale[i] = pcs[i].scale;
+    s.p[i] = pcs[i].p;
+    s.pinv[i] = pcs[i].pinv;
+    s.gc[i] = gc[i];
+    s.scale[i] = pcs[i].scale;
   }
   for (int i = threadIdx.x; i < L; i += kBlock) {
-    s_m[i] = mlimbs[i];
-    s_h[i] = hlimbs[i];
+    s.m[i] = mlimbs[i];
+    s.h[i] = hlimbs[i];
   }
-  __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (c >= C) return;
+}
+
+template <int PN>
+__device__ __forceinline__ void garner_body(const GarnerShared<PN>& s,
+                                            const uint32_t* __restrict__ coef,
+                                            uint32_t* __restrict__ out, int64_t c, int64_t C,
+                                            int pn, int L) {
   uint32_t alpha[PN];
 #pragma unroll
   for (int i = 0; i < PN; ++i) {
     if (i < pn) {
-      const uint32_t p = s_p[i], pinv = s_pinv[i];
+      const uint32_t p = s.p[i], pinv = s.pinv[i];
       // residue out of Montgomery form and divided by G (the inverse-DFT factor)
-      const uint32_t x = mm(coef[(int64_t)i * C + c], s_scale[i], p, pinv);
+      const uint32_t x = mm(coef[(int64_t)i * C + c], s.scale[i], p, pinv);
       uint32_t acc = 0u;
 #pragma unroll
       for (int j = 0; j < PN; ++j) {
-        if (j < i) acc = addm(acc, mm(alpha[j], s_gw[i * PN + j], p, pinv), p);
+        if (j < i) acc = addm(acc, mm(alpha[j], s.gw[i * PN + j], p, pinv), p);
       }
-      alpha[i] = mm(subm(x, acc, p), s_gc[i], p, pinv);
+      alpha[i] = mm(subm(x, acc, p), s.gc[i], p, pinv);
     } else {
       alpha[i] = 0u;
     }
@@ -216,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void garner_kernel(
 #pragma unroll
   for (int i = PN - 1; i >= 0; --i) {
     if (i < pn) {
-      const uint32_t pi = (i == pn - 1) ? 0u : s_p[i];
+      const uint32_t pi = (i == pn - 1) ? 0u : s.p[i];
       uint64_t carry = alpha[i];
 #pragma unroll
       for (int l = 0; l < PN; ++l) {
@@ -230,14 +313,14 @@ __global__ __launch_bounds__(kBlock) void garner_kernel(
   int cmp = 0;
 #pragma unroll
   for (int l = PN - 1; l >= 0; --l) {
-    if (l < L && cmp == 0) cmp = (X[l] > s_h[l]) ? 1 : (X[l] < s_h[l] ? -1 : 0);
+    if (l < L && cmp == 0) cmp = (X[l] > s.h[l]) ? 1 : (X[l] < s.h[l] ? -1 : 0);
   }
   if (cmp > 0) {
     uint32_t borrow = 0u;
 #pragma unroll
     for (int l = 0; l < PN; ++l) {
       if (l < L) {
-        const uint64_t d = (uint64_t)X[l] - s_m[l] - borrow;
+        const uint64_t d = (uint64_t)X[l] - s.m[l] - borrow;
         X[l] = (uint32_t)d;
         borrow = (uint32_t)(d >> 63);
       }
@@ -250,6 +333,37 @@ __global__ __launch_bounds__(kBlock) void garner_kernel(
   }
 }
 
+template <int PN>
+__global__ __launch_bounds__(kBlock) void garner_kernel(
+    const uint32_t* __restrict__ coef, uint32_t* __restrict__ out, int64_t C, int pn, int L,
+    const PrimeConst* __restrict__ pcs, const uint32_t* __restrict__ gw,
+    const uint32_t* __restrict__ gc, const uint32_t* __restrict__ mlimbs,
+    const uint32_t* __restrict__ hlimbs) {
+  __shared__ GarnerShared<PN> s;
+  garner_load<PN>(s, pn, L, pcs, gw, gc, mlimbs, hlimbs);
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (c < C) garner_body<PN>(s, coef, out, c, C, pn, L);
+}
+
+template <int PN>
+__global__ __launch_bounds__(kBlock) void garner_batch_kernel(
+    const BGarner* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws,
+    uint32_t* __restrict__ out, const int64_t* __restrict__ out_offsets) {
+  __shared__ GarnerShared<PN> s;
+  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
+    const BGarner& d = desc[find_desc(desc, ndesc, vb)];
+    garner_load<PN>(s, d.pn, d.L, d.pc, d.gw, d.gc, d.ml, d.hl);
+    __syncthreads();
+    const int64_t c = (vb - d.block0) * kBlock + threadIdx.x;
+    if (c < d.C) {
+      garner_body<PN>(s, (const uint32_t*)(ws + d.coef_off), out + out_offsets[d.mat], c, d.C,
+                      d.pn, d.L);
+    }
+    __syncthreads();  // the next virtual block reloads the tables
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // launch helpers
 // ------------------------------------------------------------------------------------
@@ -257,9 +371,10 @@ template <int M>
 hipError_t launch_expand_m(const MatPlan& P, const uint32_t* in, uint32_t* out, int64_t outer,
                            int v, int64_t inner, hipStream_t st) {
   const int64_t B = (int64_t)P.pn * P.nent;
-  const int64_t work = B * outer * inner;
+  const int JC = expand_outputs_per_thread(P.N[v], inner);
+  const int64_t work = B * outer * (P.N[v] / JC) * inner;
   hipLaunchKernelGGL(expand_kernel<M>, dim3(blocks_for(work)), dim3(kBlock), 0, st, in, out, B,
-                     outer, P.m[v], P.N[v], inner, P.nent, P.d_tw + P.tw_off[v], P.tw_stride,
+                     outer, P.m[v], P.N[v], JC, inner, P.nent, P.d_tw + P.tw_off[v], P.tw_stride,
                      P.d_pc, P.d_zero);
   return hipGetLastError();
 }
@@ -301,23 +416,39 @@ hipError_t launch_det_ng(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hi
   return det_fused_launch<N, GL>(f, st);
 }
 
-template <int N>
-hipError_t launch_det_n(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hipStream_t st) {
-  switch (P.det_lanes) {
+template <int N, int GL>
+struct SingleDet {
+  static hipError_t run(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hipStream_t st) {
+    return launch_det_ng<N, GL>(P, ws, detv, st);
+  }
+};
+
+template <int N, int GL>
+struct BatchDet {
+  static hipError_t run(const BDet* desc, int ndesc, int64_t vblocks, size_t lds, uint8_t* ws,
+                        hipStream_t st) {
+    return det_fused_batch_launch<N, GL>(desc, ndesc, vblocks, lds, ws, st);
+  }
+};
+
+// Calls F<N, GL>::run(args...) for the (order, lanes) pair if a kernel is compiled for it.
+template <template <int, int> class F, int N, typename... A>
+hipError_t det_dispatch_n(int lanes, A&&... args) {
+  switch (lanes) {
     case 1:
-      if constexpr (N <= 12) return launch_det_ng<N, 1>(P, ws, detv, st);
+      if constexpr (N <= 12) return F<N, 1>::run(std::forward<A>(args)...);
       break;
     case 2:
-      if constexpr (N >= 2 && N <= 16) return launch_det_ng<N, 2>(P, ws, detv, st);
+      if constexpr (N >= 2 && N <= 16) return F<N, 2>::run(std::forward<A>(args)...);
       break;
     case 4:
-      if constexpr (N >= 4 && N <= 24) return launch_det_ng<N, 4>(P, ws, detv, st);
+      if constexpr (N >= 4 && N <= 24) return F<N, 4>::run(std::forward<A>(args)...);
       break;
     case 8:
-      if constexpr (N >= 8) return launch_det_ng<N, 8>(P, ws, detv, st);
+      if constexpr (N >= 8) return F<N, 8>::run(std::forward<A>(args)...);
       break;
     case 16:
-      if constexpr (N >= 16) return launch_det_ng<N, 16>(P, ws, detv, st);
+      if constexpr (N >= 16) return F<N, 16>::run(std::forward<A>(args)...);
       break;
     default:
       break;
@@ -325,18 +456,31 @@ hipError_t launch_det_n(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hip
   return hipErrorInvalidValue;
 }
 
-template <int... Ns>
-hipError_t dispatch_det(std::integer_sequence<int, Ns...>, const MatPlan& P, const uint8_t* ws,
-                        uint32_t* detv, hipStream_t st) {
+template <template <int, int> class F, int... Ns, typename... A>
+hipError_t det_dispatch_seq(std::integer_sequence<int, Ns...>, int n, int lanes, A&&... args) {
   hipError_t r = hipErrorInvalidValue;
-  ((P.n == Ns + 1 ? (r = launch_det_n<Ns + 1>(P, ws, detv, st), 0) : 0), ...);
+  ((n == Ns + 1 ? (r = det_dispatch_n<F, Ns + 1>(lanes, std::forward<A>(args)...), 0) : 0), ...);
   return r;
+}
+
+template <template <int, int> class F, typename... A>
+hipError_t det_dispatch(int n, int lanes, A&&... args) {
+  return det_dispatch_seq<F>(std::make_integer_sequence<int, kMaxN>{}, n, lanes,
+                             std::forward<A>(args)...);
 }
 
 template <int PN>
 hipError_t launch_garner_pn(const MatPlan& P, const uint32_t* coef, uint32_t* out, hipStream_t st) {
   hipLaunchKernelGGL(garner_kernel<PN>, dim3(blocks_for(P.C)), dim3(kBlock), 0, st, coef, out, P.C,
                      P.pn, P.L, P.d_pc, P.d_gw, P.d_gc, P.d_mlimbs, P.d_hlimbs);
+  return hipGetLastError();
+}
+
+template <int PN>
+hipError_t launch_garner_batch(const BGarner* desc, int ndesc, int64_t vblocks, uint8_t* ws,
+                               uint32_t* out, const int64_t* out_offsets, hipStream_t st) {
+  hipLaunchKernelGGL(garner_batch_kernel<PN>, dim3(persistent_grid(vblocks)), dim3(kBlock), 0, st,
+                     desc, ndesc, vblocks, ws, out, out_offsets);
   return hipGetLastError();
 }
 
@@ -352,6 +496,21 @@ bool det_config_supported(int n, int lanes) {
     case 16: return n >= 16;
     default: return false;
   }
+}
+
+int expand_outputs_per_thread(int Nv, int64_t inner) {
+  // enough threads per line that a wave covers at least 64 consecutive outputs
+  int nJB = 1;
+  while (nJB < Nv && nJB * inner < 64) nJB <<= 1;
+  return Nv / nJB;
+}
+
+int intt_lines_per_block(int64_t lines, int Nv, int pn) {
+  // as many lines as fit in kTileElems, fewer while that leaves under ~1024 blocks (W stays
+  // a power of two, so it divides inner when inner >= W)
+  int W = kTileElems / Nv;
+  while (W > 1 && ((lines + W - 1) / W) * pn < 1024) W >>= 1;
+  return W;
 }
 
 hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st) {
@@ -381,8 +540,8 @@ hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
 }
 
 hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st) {
-  return dispatch_det(std::make_integer_sequence<int, kMaxN>{}, P, ws,
-                      (uint32_t*)(ws + P.off_detv), st);
+  return det_dispatch<SingleDet>(P.n, P.det_lanes, P, (const uint8_t*)ws,
+                                 (uint32_t*)(ws + P.off_detv), st);
 }
 
 hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
@@ -398,16 +557,13 @@ hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
     const int Nv = P.N[v];
     int logN = 0;
     while ((1 << logN) < Nv) ++logN;
-    // W lines per block: as many as fit in kTileElems, fewer while that leaves under ~1024
-    // blocks for the pass (W stays a power of two, so it divides inner when inner >= W)
     const int64_t lines = outer * inner;
-    int W = kTileElems / Nv;
-    while (W > 1 && ((lines + W - 1) / W) * P.pn < 1024) W >>= 1;
+    const int W = intt_lines_per_block(lines, Nv, P.pn);
     const int64_t tiles = (lines + W - 1) / W;
     const size_t lds = (size_t)Nv * W * sizeof(uint32_t);
     hipLaunchKernelGGL(intt_kernel, dim3((unsigned)(tiles * P.pn)), dim3(kBlock), lds, st, in, out,
-                       P.pn, outer, Nv, logN, inner, P.D[v] + 1, W, P.d_itw + P.tw_off[v],
-                       P.tw_stride, P.d_pc);
+                       outer, Nv, logN, inner, P.D[v] + 1, W, P.d_itw + P.tw_off[v], P.tw_stride,
+                       P.d_pc);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     in = out;
@@ -421,6 +577,42 @@ hipError_t run_reconstruct(const MatPlan& P, uint8_t* ws, uint32_t* out, hipStre
   if (P.pn <= 8) return launch_garner_pn<8>(P, coef, out, st);
   if (P.pn <= 16) return launch_garner_pn<16>(P, coef, out, st);
   return launch_garner_pn<32>(P, coef, out, st);
+}
+
+// ------------------------------------------------------------------------------------
+// batched launches
+// ------------------------------------------------------------------------------------
+hipError_t batch_reduce(const BReduce* desc, int ndesc, int64_t vblocks, const int64_t* coeffs,
+                        const int64_t* coeff_offsets, uint8_t* ws, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_batch_kernel, dim3(persistent_grid(vblocks)), dim3(kBlock), 0, st,
+                     desc, ndesc, vblocks, coeffs, coeff_offsets, ws);
+  return hipGetLastError();
+}
+
+hipError_t batch_expand(const BExpand* desc, int ndesc, int64_t vblocks, uint8_t* ws,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(expand_batch_kernel, dim3(persistent_grid(vblocks)), dim3(kBlock), 0, st,
+                     desc, ndesc, vblocks, ws);
+  return hipGetLastError();
+}
+
+hipError_t batch_intt(const BIntt* desc, int ndesc, int64_t vblocks, size_t lds, uint8_t* ws,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(intt_batch_kernel, dim3(persistent_grid(vblocks)), dim3(kBlock), lds, st,
+                     desc, ndesc, vblocks, ws);
+  return hipGetLastError();
+}
+
+hipError_t batch_garner(const BGarner* desc, int ndesc, int64_t vblocks, int pnmax, uint8_t* ws,
+                        uint32_t* out, const int64_t* out_offsets, hipStream_t st) {
+  if (pnmax <= 8) return launch_garner_batch<8>(desc, ndesc, vblocks, ws, out, out_offsets, st);
+  if (pnmax <= 16) return launch_garner_batch<16>(desc, ndesc, vblocks, ws, out, out_offsets, st);
+  return launch_garner_batch<32>(desc, ndesc, vblocks, ws, out, out_offsets, st);
+}
+
+hipError_t batch_det(int n, int lanes, const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
+                     uint8_t* ws, hipStream_t st) {
+  return det_dispatch<BatchDet>(n, lanes, desc, ndesc, vblocks, lds, ws, st);
 }
 
 }  // namespace pd

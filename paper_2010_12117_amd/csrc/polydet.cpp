@@ -4,10 +4,12 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
 
+#include "batch_plan.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -23,9 +25,19 @@ struct StageTimer {
   bool ready = false;
 };
 
+// Device state of a batched solve: the descriptor tables and the offset arrays.
+struct BatchState {
+  pd::BatchPlan bp;
+  uint8_t* d_desc = nullptr;
+  int64_t* d_offsets = nullptr;          // [2][count]: coefficient offsets, output offsets
+  std::vector<int64_t> h_offsets;        // what d_offsets holds
+  bool plain = false;
+};
+
 struct polydet_plan_s {
   pd::Plan plan;
   StageTimer* timer = nullptr;
+  BatchState* batch = nullptr;
 };
 
 namespace {
@@ -49,6 +61,37 @@ polydet_status check_shape(const polydet_shape* s, pd::ShapeIn* out) {
   out->coeff_bits = s->coeff_bits;
   if (s->nvars < 0 || s->nvars > POLYDET_MAX_VARS) return fail(POLYDET_EINVAL, "nvars must be in 0..8");
   for (int v = 0; v < POLYDET_MAX_VARS; ++v) out->deg[v] = v < s->nvars ? s->deg[v] : 0;
+  return POLYDET_OK;
+}
+
+constexpr size_t kBatchBudget = size_t(16) << 30;  // default workspace per chunk of a batch
+
+size_t batch_budget() {
+  const char* v = std::getenv("POLYDET_BATCH_BUDGET_MB");
+  if (v && *v) {
+    const long long mb = std::atoll(v);
+    if (mb > 0) return (size_t)mb << 20;
+  }
+  return kBatchBudget;
+}
+
+polydet_status make_batch(polydet_plan_s* h, uint32_t flags) {
+  BatchState* B = new (std::nothrow) BatchState();
+  if (!B) return fail(POLYDET_ENOMEM, "host allocation failed");
+  h->batch = B;
+  B->plain = (flags & POLYDET_BATCH_PLAIN) != 0;
+  if (B->plain) return POLYDET_OK;
+  std::string err = pd::build_batch(h->plan.mats, batch_budget(), &B->bp);
+  if (!err.empty()) return fail(POLYDET_EINVAL, err);
+  h->plan.ws_bytes = B->bp.ws_bytes;
+  hipError_t e = hipMalloc((void**)&B->d_desc, std::max<size_t>(B->bp.desc_blob.size(), 256));
+  if (e != hipSuccess) return hip_fail(e, "batch descriptors");
+  if (!B->bp.desc_blob.empty()) {
+    e = hipMemcpy(B->d_desc, B->bp.desc_blob.data(), B->bp.desc_blob.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batch descriptors");
+  }
+  e = hipMalloc((void**)&B->d_offsets, 2 * sizeof(int64_t) * h->plan.mats.size());
+  if (e != hipSuccess) return hip_fail(e, "batch offsets");
   return POLYDET_OK;
 }
 
@@ -98,6 +141,13 @@ polydet_status make_plan(const polydet_shape* shapes, int32_t count,
   if (up != 0) {
     delete h;
     return hip_fail((hipError_t)up, "uploading plan tables");
+  }
+  if (batch) {
+    polydet_status bs = make_batch(h, flags);
+    if (bs != POLYDET_OK) {
+      polydet_plan_destroy(h);
+      return bs;
+    }
   }
   if (flags & POLYDET_STAGE_TIMING) {
     h->timer = new (std::nothrow) StageTimer();
@@ -241,11 +291,65 @@ polydet_status polydet_solve(polydet_plan_t plan, const int64_t* d_coeffs, uint3
   return run_one(P, d_coeffs, d_out, (uint8_t*)d_workspace, (hipStream_t)stream, plan->timer);
 }
 
+static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
+                           const int64_t* coeff_offsets, uint32_t* d_out,
+                           const int64_t* out_offsets, uint8_t* ws, hipStream_t st) {
+  BatchState* B = plan->batch;
+  const size_t count = plan->plan.mats.size();
+  // device copies of the offsets, refreshed on the stream only when they change
+  bool same = B->h_offsets.size() == 2 * count;
+  for (size_t i = 0; same && i < count; ++i) {
+    same = B->h_offsets[i] == coeff_offsets[i] && B->h_offsets[count + i] == out_offsets[i];
+  }
+  if (!same) {
+    B->h_offsets.assign(coeff_offsets, coeff_offsets + count);
+    B->h_offsets.insert(B->h_offsets.end(), out_offsets, out_offsets + count);
+    // ordered after earlier work on the stream; waited for, since the host copy is
+    // pageable and replaced by the next call with other offsets
+    hipError_t e = hipMemcpyAsync(B->d_offsets, B->h_offsets.data(), 2 * count * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "batch offsets");
+  }
+  const int64_t* d_coff = B->d_offsets;
+  const int64_t* d_ooff = B->d_offsets + count;
+  for (const pd::BLaunch& L : B->bp.launches) {
+    const void* desc = B->d_desc + L.desc_off;
+    hipError_t e = hipSuccess;
+    switch (L.kind) {
+      case pd::BLaunch::kReduce:
+        e = pd::batch_reduce((const pd::BReduce*)desc, L.ndesc, L.vblocks, d_coeffs, d_coff, ws, st);
+        break;
+      case pd::BLaunch::kExpand:
+        e = pd::batch_expand((const pd::BExpand*)desc, L.ndesc, L.vblocks, ws, st);
+        break;
+      case pd::BLaunch::kDet:
+        e = pd::batch_det(L.n, L.lanes, (const pd::BDet*)desc, L.ndesc, L.vblocks, L.lds, ws, st);
+        break;
+      case pd::BLaunch::kIntt:
+        e = pd::batch_intt((const pd::BIntt*)desc, L.ndesc, L.vblocks, L.lds, ws, st);
+        break;
+      case pd::BLaunch::kGarner:
+        e = pd::batch_garner((const pd::BGarner*)desc, L.ndesc, L.vblocks, L.pnmax, ws, d_out,
+                             d_ooff, st);
+        break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+  }
+  for (int i : B->bp.singles) {
+    polydet_status r = run_one(plan->plan.mats[i], d_coeffs + coeff_offsets[i],
+                               d_out + out_offsets[i], ws, st, nullptr);
+    if (r != POLYDET_OK) return r;
+  }
+  return POLYDET_OK;
+}
+
 polydet_status polydet_solve_batch(polydet_plan_t plan, const int64_t* d_coeffs,
                                    const int64_t* coeff_offsets, uint32_t* d_out,
                                    const int64_t* out_offsets, void* d_workspace,
                                    size_t workspace_bytes, void* stream) {
   if (!plan) return fail(POLYDET_EINVAL, "NULL plan");
+  if (!plan->plan.batch) return fail(POLYDET_EINVAL, "single-matrix plans are solved by polydet_solve");
   if (!d_coeffs || !d_out || !d_workspace || !coeff_offsets || !out_offsets)
     return fail(POLYDET_EINVAL, "NULL buffer or offsets");
   if (workspace_bytes < plan->plan.ws_bytes) return fail(POLYDET_EINVAL, "workspace too small");
@@ -255,6 +359,10 @@ polydet_status polydet_solve_batch(polydet_plan_t plan, const int64_t* d_coeffs,
   }
   polydet_status st = check_device(plan->plan);
   if (st != POLYDET_OK) return st;
+  if (plan->batch && !plan->batch->plain) {
+    return run_batched(plan, d_coeffs, coeff_offsets, d_out, out_offsets, (uint8_t*)d_workspace,
+                       (hipStream_t)stream);
+  }
   for (size_t i = 0; i < plan->plan.mats.size(); ++i) {
     st = run_one(plan->plan.mats[i], d_coeffs + coeff_offsets[i], d_out + out_offsets[i],
                  (uint8_t*)d_workspace, (hipStream_t)stream, plan->timer);
@@ -291,6 +399,11 @@ void polydet_plan_destroy(polydet_plan_t plan) {
       }
     }
     delete plan->timer;
+  }
+  if (plan->batch) {
+    if (plan->batch->d_desc) (void)hipFree(plan->batch->d_desc);
+    if (plan->batch->d_offsets) (void)hipFree(plan->batch->d_offsets);
+    delete plan->batch;
   }
   if (plan->plan.d_tables) (void)hipFree(plan->plan.d_tables);
   delete plan;

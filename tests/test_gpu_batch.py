@@ -1,0 +1,279 @@
+"""Batched solves (polydet_solve_batch): thousands of matrices of uneven order, variable count
+and degree in chunked persistent launches. Bit-exact against the plain per-matrix path,
+single-matrix solves and the oracle; also across chunk boundaries, for matrices that fall
+back to single solves, and on replays of a captured HIP graph."""
+import os
+
+import numpy as np
+import pytest
+
+import paper_2010_12117_amd as pdm
+from paper_2010_12117_amd import binding as B
+import workloads as W
+from oracle import det as OD
+from oracle import plan as PL
+
+from helpers import box_to_dict
+
+pytestmark = pytest.mark.gpu
+
+
+def pack(mats, pl):
+    import torch
+    coeff_off, out_off = [], []
+    c = o = 0
+    for a, info in zip(mats, pl.infos):
+        coeff_off.append(c)
+        out_off.append(o)
+        c += a.size
+        o += info["ncoeff"] * info["limbs"]
+    flat = np.concatenate([np.ascontiguousarray(a, dtype=np.int64).reshape(-1) for a in mats])
+    d_coeffs = torch.from_numpy(flat).cuda()
+    d_out = torch.zeros(max(o, 1), dtype=torch.int32, device="cuda")
+    return d_coeffs, coeff_off, d_out, out_off
+
+
+def unpack(pl, d_out, out_off):
+    host = d_out.cpu().numpy()
+    res = []
+    for info, off in zip(pl.infos, out_off):
+        L = info["limbs"]
+        vals = B.limbs_to_ints(host[off:off + info["ncoeff"] * L].reshape(-1, L))
+        box = tuple(d + 1 for d in info["D"])
+        arr = np.empty(len(vals), dtype=object)
+        for i, v in enumerate(vals):
+            arr[i] = v
+        res.append(arr.reshape(box) if box else arr.reshape(()))
+    return res
+
+
+def solve_batch(mats, flags=0):
+    import torch
+    pl = pdm.plan_batch(mats, flags=flags)
+    d_coeffs, co, d_out, oo = pack(mats, pl)
+    pdm.solve_batch_device(pl, d_coeffs, co, d_out, oo)
+    torch.cuda.synchronize()
+    return unpack(pl, d_out, oo), pl
+
+
+def solve_single(a):
+    import torch
+    n, deg = B.shape_of(a)
+    pl = pdm.plan(n, deg, host_coeffs=a)
+    out, _ = pdm.solve_device(pl, torch.from_numpy(np.ascontiguousarray(a)).cuda())
+    torch.cuda.synchronize()
+    vals = B.limbs_to_ints(out.cpu().numpy())
+    arr = np.empty(len(vals), dtype=object)
+    for i, v in enumerate(vals):
+        arr[i] = v
+    box = tuple(d + 1 for d in pl.info["D"])
+    return arr.reshape(box) if box else arr.reshape(())
+
+
+def oracle_cost(a):
+    n, deg = B.shape_of(a)
+    return int(np.prod([n * d + 1 for d in deg])) * n ** 3
+
+
+def mixed_batch(seed=0, count=40):
+    rng = np.random.default_rng(500 + seed)
+    mats = []
+    for _ in range(count):
+        n = int(rng.integers(1, 13))
+        k = int(rng.integers(1, 4))
+        deg = tuple(int(x) for x in rng.integers(0, 3, size=k))
+        mats.append(W.random_matrix(rng, n, deg, -50, 50, zero_prob=float(rng.uniform(0, 0.4))))
+    # kinds that take the single-matrix path inside a batch
+    mats.append(np.array([[3, -7], [2 ** 40, 5]], dtype=np.int64))  # no variables
+    mats.append(W.random_matrix(rng, 3, (9, 1), -5, 5))  # 10 coefficients in a later variable
+    mats.append(W.random_matrix(rng, 3, (1, 9), -5, 5))
+    mats.append(np.zeros((4, 4, 2, 2), dtype=np.int64))  # zero matrix
+    return mats
+
+
+def test_batch_matches_plain_single_and_oracle():
+    mats = mixed_batch()
+    got, pl = solve_batch(mats)
+    plain, _ = solve_batch(mats, flags=pdm.BATCH_PLAIN)
+    for i, a in enumerate(mats):
+        assert box_to_dict(got[i]) == box_to_dict(plain[i]), i
+        n, deg = B.shape_of(a)
+        expect = OD.det_pointwise(a, PL.det_degree_bound_from_shape(n, deg))
+        assert box_to_dict(got[i]) == box_to_dict(expect), i
+
+
+def test_batch_across_chunks(monkeypatch):
+    mats = W.config4(count=24)
+    monkeypatch.setenv("POLYDET_BATCH_BUDGET_MB", "8")
+    got, _ = solve_batch(mats)
+    monkeypatch.delenv("POLYDET_BATCH_BUDGET_MB")
+    whole, _ = solve_batch(mats)
+    for i, a in enumerate(mats):
+        assert box_to_dict(got[i]) == box_to_dict(whole[i]), i
+    cheap = sorted(range(len(mats)), key=lambda i: oracle_cost(mats[i]))[:6]
+    for i in cheap:
+        assert box_to_dict(got[i]) == box_to_dict(solve_single(mats[i])), i
+        n, deg = B.shape_of(mats[i])
+        expect = OD.det_pointwise(mats[i], PL.det_degree_bound_from_shape(n, deg))
+        assert box_to_dict(got[i]) == box_to_dict(expect), i
+
+
+def test_batch_graph_replay():
+    # a captured batched solve replays bit-identically, with eager work between replays
+    import torch
+    mats = mixed_batch(seed=1, count=24)
+    pl = pdm.plan_batch(mats)
+    d_coeffs, co, d_out, oo = pack(mats, pl)
+    ws = torch.empty(pl.infos[0]["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        pdm.solve_batch_device(pl, d_coeffs, co, d_out, oo, workspace=ws, stream=stream)
+    stream.synchronize()
+    eager = d_out.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        pdm.solve_batch_device(pl, d_coeffs, co, d_out, oo, workspace=ws, stream=stream)
+    for _ in range(3):
+        d_out.fill_(-1)
+        junk = torch.randn(1 << 20, device="cuda") * 2
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(d_out, eager)
+        del junk
+
+
+Q31 = 2147483629  # a prime below 2^31 that is not of the NTT form used by the library
+
+
+def limbs_mod_q(limbs, q):
+    """Two's-complement little-endian uint32 limb rows -> values mod q (vectorised)."""
+    limbs = np.asarray(limbs).view(np.uint32).astype(np.uint64)
+    L = limbs.shape[1]
+    acc = np.zeros(limbs.shape[0], dtype=np.uint64)
+    for l in range(L):
+        acc = (acc + (limbs[:, l] % q) * np.uint64(pow(2, 32 * l, q))) % q
+    neg = (limbs[:, L - 1] >> np.uint64(31)).astype(bool)
+    wrap = np.uint64(pow(2, 32 * L, q))
+    acc[neg] = (acc[neg] + np.uint64(q) - wrap) % q
+    return acc
+
+
+def eval_box_mod_q(vals, box, point, q):
+    """sum_e vals[e] prod_v point_v^{e_v} mod q for a dense box (first variable slowest)."""
+    arr = vals.reshape(box) if box else vals.reshape(())
+    for v in range(len(box) - 1, -1, -1):
+        pw = np.array([pow(int(point[v]), e, q) for e in range(box[v])], dtype=np.uint64)
+        arr = (arr * pw) % q
+        arr = np.sum(arr, axis=-1, dtype=np.uint64) % q if arr.ndim else arr
+    return int(arr)
+
+
+def device_values_at_point(d_out, off, C, L, box, point, q):
+    """The output polynomial (limbs on the device) reduced mod q and evaluated at `point`,
+    with torch int64 arithmetic on the device (every product stays below 2^62)."""
+    import torch
+    limbs = d_out[off:off + C * L].view(C, L).to(torch.int64) & 0xFFFFFFFF
+    acc = torch.zeros(C, dtype=torch.int64, device=d_out.device)
+    for l in range(L):
+        acc = (acc + (limbs[:, l] % q) * pow(2, 32 * l, q)) % q
+    neg = (limbs[:, L - 1] >> 31) == 1
+    acc = torch.where(neg, (acc + q - pow(2, 32 * L, q)) % q, acc)
+    arr = acc.view(box) if box else acc.view(())
+    for v in range(len(box) - 1, -1, -1):
+        pw = torch.tensor([pow(int(point[v]), e, q) for e in range(box[v])], dtype=torch.int64,
+                          device=d_out.device)
+        arr = (arr * pw) % q
+        arr = arr.sum(dim=-1) % q if arr.dim() else arr  # at most 161 terms < 2^31 each
+    return int(arr.item())
+
+
+def det_mod_q_stack(A, q):
+    """Determinants mod q of a stack of matrices (numpy uint64 [count, n, n], entries < q) by
+    Gaussian elimination with the first nonzero pivot, vectorised over the stack."""
+    A = A.copy()
+    count, n, _ = A.shape
+    det = np.ones(count, dtype=np.uint64)
+    alive = np.ones(count, dtype=bool)
+    idx = np.arange(count)
+    for k in range(n):
+        nz = A[:, k:, k] != 0
+        has = nz.any(axis=1)
+        alive &= has
+        r = k + np.argmax(nz, axis=1)
+        swap = (r != k) & has
+        rows_k = A[idx, k].copy()
+        A[idx, k] = A[idx, r]
+        A[idx, r] = rows_k
+        det = np.where(swap, (q - det) % q, det)
+        piv = np.where(has, A[:, k, k], 1).astype(np.uint64)
+        det = det * piv % q
+        inv = np.ones(count, dtype=np.uint64)
+        base, e = piv.copy(), q - 2
+        while e:
+            if e & 1:
+                inv = inv * base % q
+            base = base * base % q
+            e >>= 1
+        for i in range(k + 1, n):
+            f = A[:, i, k] * inv % q
+            A[:, i, k:] = (A[:, i, k:] + (q - f)[:, None] * A[:, k, k:]) % q
+    return np.where(alive, det, 0)
+
+
+def test_det_mod_q_stack_matches_oracle_steps():
+    from oracle import modular as OM
+    rng = np.random.default_rng(1)
+    for n in [1, 2, 5, 9]:
+        A = rng.integers(0, Q31, size=(20, n, n)).astype(np.uint64)
+        A[rng.random((20, n, n)) < 0.4] = 0
+        got = det_mod_q_stack(A, Q31)
+        for t in range(20):
+            assert int(got[t]) == OM.det_mod(A[t].astype(object).tolist(), Q31)
+
+
+def test_config4_all_matrices_identity_and_cheap_oracle():
+    """Every one of the 4096 matrices: the batched result, reduced mod an independent prime
+    q and evaluated at a seeded random point, equals det M(point) mod q (a false pass has
+    probability at most deg/q per matrix, Schwartz-Zippel). The cheapest matrices are also
+    compared with the oracle exactly."""
+    import torch
+    mats = W.config4()
+    pl = pdm.plan_batch(mats)
+    d_coeffs, co, d_out, oo = pack(mats, pl)
+    pdm.solve_batch_device(pl, d_coeffs, co, d_out, oo)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4242)
+    q = Q31
+    lhs, points = [], []
+    for a, info, off in zip(mats, pl.infos, oo):
+        n, deg = B.shape_of(a)
+        point = [int(x) for x in rng.integers(1, q, size=len(deg))]
+        points.append(point)
+        box = tuple(d + 1 for d in info["D"])
+        lhs.append(device_values_at_point(d_out, off, info["ncoeff"], info["limbs"], box, point, q))
+    # det M(point) mod q, grouped by order
+    by_n = {}
+    for t, a in enumerate(mats):
+        by_n.setdefault(a.shape[0], []).append(t)
+    for n, ts in by_n.items():
+        stack = np.zeros((len(ts), n, n), dtype=np.uint64)
+        for s_, t in enumerate(ts):
+            a = mats[t]
+            k = a.ndim - 2
+            vals = (a % q).astype(np.uint64)
+            for v in range(k - 1, -1, -1):
+                pw = np.array([pow(points[t][v], e, q) for e in range(a.shape[2 + v])],
+                              dtype=np.uint64)
+                vals = np.sum((vals * pw) % q, axis=-1, dtype=np.uint64) % q
+            stack[s_] = vals
+        dets = det_mod_q_stack(stack, q)
+        for s_, t in enumerate(ts):
+            assert lhs[t] == int(dets[s_]), t
+    cheap = sorted(range(len(mats)), key=lambda i: oracle_cost(mats[i]))[:12]
+    for i in cheap:
+        info, off = pl.infos[i], oo[i]
+        L = info["limbs"]
+        vals = B.limbs_to_ints(d_out[off:off + info["ncoeff"] * L].cpu().numpy().reshape(-1, L))
+        n, deg = B.shape_of(mats[i])
+        expect = OD.det_pointwise(mats[i], PL.det_degree_bound_from_shape(n, deg)).reshape(-1)
+        assert vals == [int(x) for x in expect], i
