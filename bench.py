@@ -29,6 +29,21 @@ UPDATES_PER_CLK_CU = 1.0 / (4 / 64 + 2 / 128)
 ALU_PEAK_UPDATES = CU * CLOCK_HZ * UPDATES_PER_CLK_CU
 
 
+# HBM bytes per launch of the fused elimination kernel on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB copy (profiles/config2_hbm_traffic.md),
+# valid only for the kernel sources they were taken with (hash of det_impl.h + modarith.h).
+DET_TRAFFIC = {"sources_sha256_16": "0c3cafd694df0f5e", "bytes": 94.9e6 + 14.7e6}
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ("paper_2010_12117_amd/csrc/det_impl.h", "paper_2010_12117_amd/csrc/modarith.h"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def det_updates(n: int) -> int:
     """Elimination updates of one determinant: sum_{m=1}^{n-1} m^2."""
     return (n - 1) * n * (2 * n - 1) // 6
@@ -127,16 +142,78 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_serving(args):
+    """Serving: a Poisson stream of determinant jobs (n 4..32, 2-3 variables, degree 1-5,
+    coefficients in [-2^16, 2^16], 1% replaced by 32x32 trivariate degree-5 jobs) through the
+    continuous-batching server; the rate is rho times the capacity measured by submitting
+    every job at once. Reports p50/p99 latency and throughput per rho."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2010_12117_amd import serving as S
+
+    rng = W.rng_for(5)
+    jobs = [W.config5_job(rng) for _ in range(args.jobs)]
+    large = sum(1 for a in jobs if a.shape[0] == 32 and a.ndim == 5 and a.shape[2] == 6)
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def run(rate):
+        srv = S.Server(memory_budget=budget, slots=args.slots)
+        arr = S.poisson_arrivals(np.random.default_rng(77), len(jobs), rate) if rate else None
+        t0 = time.perf_counter()
+        futs = []
+        for i, a in enumerate(jobs):
+            if arr is not None:
+                wait = arr[i] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+            futs.append(srv.submit(a))
+        for f in futs:
+            f.result()
+        makespan = time.perf_counter() - t0
+        srv.close()
+        st = srv.stats()
+        st["makespan_s"] = makespan
+        st["jobs_per_s"] = len(jobs) / makespan
+        return st
+
+    run(0)  # warm-up: plans, kernels, allocator
+    torch.cuda.synchronize()
+    cap = run(0)
+    capacity = cap["jobs_per_s"]
+    out = {"capacity": cap}
+    for rho in (0.5, 0.8):
+        out[f"rho_{rho}"] = run(rho * capacity)
+    line = {
+        "metric": "serving: p50/p99 latency and throughput of exact determinant jobs, 1 GPU",
+        "value": out["rho_0.8"]["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic (seeded)",
+        "config": {"workload": f"{len(jobs)} Poisson-arriving jobs, n 4..32, 2-3 variables, "
+                               f"degree 1-5, coefficients U[-2^16,2^16], {large} of them "
+                               "32x32 trivariate degree 5",
+                   "slots": args.slots, "memory_budget_gb": args.serve_budget_gb},
+        "results": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config4"],
+    ap.add_argument("--workload", default="config2", choices=["config2", "config4", "config5"],
                     help="config2: the 12x12 trivariate matrix (default); config4: the batch "
                          "of 4096 uneven matrices, batched against plain")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--jobs", type=int, default=2000, help="serving: number of jobs")
+    ap.add_argument("--slots", type=int, default=4, help="serving: jobs in flight")
+    ap.add_argument("--serve-budget-gb", type=float, default=96.0,
+                    help="serving: device memory for jobs in flight")
+    ap.add_argument("--det-lanes", type=int, default=0,
+                    help="lanes per determinant (1, 2, 4, 8, 16); 0 = the plan's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before the timed loop, copy 1 GiB device to device once (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -149,6 +226,9 @@ def main():
     if args.workload == "config4":
         bench_batch(args)
         return
+    if args.workload == "config5":
+        bench_serving(args)
+        return
 
     import numpy as np
     import torch
@@ -158,7 +238,10 @@ def main():
 
     arr = W.config2()
     n, deg = 12, (3, 3, 3)
-    pl = pdm.plan(n, deg, host_coeffs=arr, flags=pdm.STAGE_TIMING)
+    flags = pdm.STAGE_TIMING
+    if args.det_lanes:
+        flags |= pdm.DET_LANES_LOG2(args.det_lanes.bit_length() - 1)
+    pl = pdm.plan(n, deg, host_coeffs=arr, flags=flags)
     info = pl.info
     pn, G = info["pn"], info["G"]
     dev = torch.device("cuda:0")
@@ -200,13 +283,15 @@ def main():
     m0 = deg[0] + 1
     eval_bytes = pn * n * n * G * 4 + pn * n * n * m0 * (G // 64) * 4
     eval_gbs = eval_bytes / (per["evaluate"] / 1e3) / 1e9
+    traffic = (DET_TRAFFIC["bytes"]
+               if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
     det_roof = {"bound": "alu", "achieved": det_achieved, "peak": ALU_PEAK_UPDATES / 1e12,
                 "unit": "T elimination-updates/s", "frac": det_achieved / (ALU_PEAK_UPDATES / 1e12),
-                "traffic": None, "kernel": "det_kernel<12,1>",
+                "traffic": traffic, "kernel": f"det_fused_kernel<{n},{info['det_lanes']}>",
                 "work_per_launch": det_work, "avg_ms": per["determinants"]}
     eval_roof = {"bound": "hbm", "achieved": eval_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": eval_gbs / HBM_PEAK_GBS, "traffic": None,
-                 "kernel": "expand_kernel<4> (3 launches)", "bytes_per_solve": eval_bytes,
+                 "kernel": "expand_kernel<4> (2 launches)", "bytes_per_solve": eval_bytes,
                  "avg_ms": per["evaluate"]}
     dominant = det_roof if per["determinants"] >= per["evaluate"] else eval_roof
 

@@ -40,11 +40,18 @@ struct BExpand {
 
 struct BDet {
   int64_t block0;
-  int64_t pre_off, detv_off, R, tw_stride, rtiles, jtiles;
+  int64_t pre_off, detv_off, den_off, R, tw_stride, rtiles, jtiles;
   int32_t N0, m0, Q, S;
   const uint32_t* tw0;
   const PrimeConst* pc;
   const uint8_t* zero;
+};
+
+struct BFinal {
+  int64_t block0;
+  int64_t detv_off, den_off, G;
+  int32_t pn, pad;
+  const PrimeConst* pc;
 };
 
 struct BIntt {
@@ -65,7 +72,7 @@ struct BGarner {
 
 // One launch of a batched solve.
 struct BLaunch {
-  enum Kind { kReduce, kExpand, kDet, kIntt, kGarner } kind;
+  enum Kind { kReduce, kExpand, kDet, kFinal, kIntt, kGarner } kind;
   size_t desc_off;     // byte offset of its descriptors in the plan's descriptor buffer
   int32_t ndesc;
   int64_t vblocks;     // virtual blocks in total
@@ -80,6 +87,8 @@ hipError_t batch_reduce(const BReduce* desc, int ndesc, int64_t vblocks, const i
                         const int64_t* coeff_offsets, uint8_t* ws, hipStream_t st);
 hipError_t batch_expand(const BExpand* desc, int ndesc, int64_t vblocks, uint8_t* ws,
                         hipStream_t st);
+hipError_t batch_final(const BFinal* desc, int ndesc, int64_t vblocks, uint8_t* ws,
+                       hipStream_t st);
 hipError_t batch_intt(const BIntt* desc, int ndesc, int64_t vblocks, size_t lds, uint8_t* ws,
                       hipStream_t st);
 hipError_t batch_garner(const BGarner* desc, int ndesc, int64_t vblocks, int pnmax, uint8_t* ws,

@@ -18,7 +18,7 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 // path needs the residues, the evaluation passes before the first variable, the
 // determinants, the interpolation ping-pong and the coefficients.
 struct Regions {
-  size_t res, tmpA, tmpB, pre, detv, iA, iB, coef, bytes;
+  size_t res, tmpA, tmpB, pre, detv, den, iA, iB, coef, bytes;
 };
 
 Regions regions_of(const MatPlan& P, size_t base) {
@@ -42,6 +42,7 @@ Regions regions_of(const MatPlan& P, size_t base) {
   r.tmpB = take(pn * P.nent * inter * 4);
   r.pre = P.k == 1 ? r.res : ((P.k - 2) % 2 == 0 ? r.tmpA : r.tmpB);
   r.detv = take(pn * P.G * 4);
+  r.den = take(pn * P.G * 4);
   size_t iinter = 0;
   for (int v = 0; v + 1 < P.k; ++v) {
     int64_t sz = 1;
@@ -197,6 +198,7 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         e.block0 = vb;
         e.pre_off = (int64_t)reg[c].pre;
         e.detv_off = (int64_t)reg[c].detv;
+        e.den_off = (int64_t)reg[c].den;
         e.R = P.G / P.N[0];
         e.tw_stride = P.tw_stride;
         e.rtiles = (e.R + P.fuse_Q - 1) / P.fuse_Q;
@@ -220,6 +222,29 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
       L.n = -kv.first.first;
       L.lanes = kv.first.second;
       L.lds = lds;
+      B.launches.push_back(L);
+    }
+    // S3 end: det = num / den for every matrix of the chunk, one launch
+    {
+      std::vector<BFinal> d;
+      int64_t vb = 0;
+      for (size_t c = 0; c < chunk.size(); ++c) {
+        const MatPlan& P = mats[chunk[c]];
+        BFinal f{};
+        f.block0 = vb;
+        f.detv_off = (int64_t)reg[c].detv;
+        f.den_off = (int64_t)reg[c].den;
+        f.G = P.G;
+        f.pn = P.pn;
+        f.pc = P.d_pc;
+        d.push_back(f);
+        vb += (finalize_threads(P.G, P.pn) + 255) / 256;
+      }
+      BLaunch L{};
+      L.kind = BLaunch::kFinal;
+      L.desc_off = push(d.data(), d.size() * sizeof(BFinal));
+      L.ndesc = (int)d.size();
+      L.vblocks = vb;
       B.launches.push_back(L);
     }
     // S4 interpolation passes: pass v covers the matrices with more than v variables

@@ -12,7 +12,8 @@ namespace pd {
 // Arguments of the fused evaluation + elimination launch (det_impl.h, det_fused_kernel).
 struct FusedDetArgs {
   const uint32_t* pre;   // [pn][n*n][m0][R]
-  uint32_t* detv;        // [pn][N0 * R]
+  uint32_t* detv;        // [pn][N0 * R] numerators of the determinants
+  uint32_t* denv;        // [pn][N0 * R] denominators
   int64_t R;             // grid points of the other variables
   int N0, m0;            // grid size and coefficient count of the first variable
   int Q, S;              // points per LDS tile, first-variable values per block
@@ -27,7 +28,7 @@ template <int N, int GL>
 hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st);
 
 template <int N, int GL>
-hipError_t det_launch(const uint32_t* eval, uint32_t* detv, int64_t npts, int pn,
+hipError_t det_launch(const uint32_t* eval, uint32_t* detv, uint32_t* denv, int64_t npts, int pn,
                       const PrimeConst* pcs, hipStream_t st);
 
 }  // namespace pd

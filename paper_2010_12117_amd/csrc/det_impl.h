@@ -42,11 +42,19 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
   }
 }
 
-// Determinant (Montgomery form) of the matrix held by the lane group; every lane of the
-// group returns it. All lanes of the wave must call this together (lane shuffles).
+// The determinant of the matrix held by the lane group as a quotient num / den (Montgomery
+// form): num = sign * pi_{n-1} (0 when some column has no pivot) and den = prod_{k<=n-3}
+// pi_k^{n-k-2} (the representative of 1 for a singular matrix, so that den is never 0).
+// The division is left to finalize_kernel, which inverts the denominators of many points
+// with one exponentiation. Every lane of the group returns the pair; all lanes of the wave
+// must call this together (lane shuffles).
+struct DetFrac {
+  uint32_t num, den;
+};
+
 template <int N, int GL>
-__device__ __forceinline__ uint32_t eliminate(uint32_t (&a)[(N + GL - 1) / GL][N], uint32_t p,
-                                              uint32_t pinv, uint32_t one) {
+__device__ __forceinline__ DetFrac eliminate(uint32_t (&a)[(N + GL - 1) / GL][N], uint32_t p,
+                                             uint32_t pinv, uint32_t one) {
   constexpr int C = (N + GL - 1) / GL;
   uint32_t flip = 0;
   bool dead = false;
@@ -89,16 +97,18 @@ __device__ __forceinline__ uint32_t eliminate(uint32_t (&a)[(N + GL - 1) / GL][N
   constexpr int sl = (N - 1) / GL, ol = (N - 1) % GL;
   const uint32_t last = bcast<GL>(a[sl][N - 1], ol);
   dead = dead || (last == 0u);
-  uint32_t d = mm(last, minv(Q, one, p, pinv), p, pinv);
-  if (flip) d = negm(d, p);
-  return dead ? 0u : d;
+  DetFrac f;
+  f.num = dead ? 0u : (flip ? negm(last, p) : last);
+  f.den = dead ? one : Q;
+  return f;
 }
 
 // Unfused form: the matrix at each point is read from the full evaluation tensor
 // eval[pn][n*n][npts].
 template <int N, int GL>
 __global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restrict__ eval,
-                                                        uint32_t* __restrict__ detv, int64_t npts,
+                                                        uint32_t* __restrict__ detv,
+                                                        uint32_t* __restrict__ denv, int64_t npts,
                                                         const PrimeConst* __restrict__ pcs) {
   constexpr int C = (N + GL - 1) / GL;
   constexpr int PER_BLOCK = kDetBlock / GL;
@@ -121,8 +131,11 @@ __global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restri
       a[c][i] = col < N ? v : 0u;
     }
   }
-  const uint32_t d = eliminate<N, GL>(a, p, pinv, one);
-  if (valid && t == 0) detv[(int64_t)prime * npts + pt] = d;
+  const DetFrac d = eliminate<N, GL>(a, p, pinv, one);
+  if (valid && t == 0) {
+    detv[(int64_t)prime * npts + pt] = d.num;
+    denv[(int64_t)prime * npts + pt] = d.den;
+  }
 }
 
 // Fused form: the last evaluation axis (the first variable, whose grid index j0 is the
@@ -137,7 +150,8 @@ __global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restri
 // One block's share of the fused kernel: prime `prime`, tile `bx` = (j-range, r-range).
 template <int N, int GL>
 __device__ __forceinline__ void det_fused_body(
-    uint32_t* tile, const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, int64_t R,
+    uint32_t* tile, const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv,
+    uint32_t* __restrict__ denv, int64_t R,
     int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
     const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, int prime, int64_t bx) {
   constexpr int C = (N + GL - 1) / GL;
@@ -229,19 +243,23 @@ __device__ __forceinline__ void det_fused_body(
         for (int i = 0; i < N; ++i) a[C - 1][i] = 0u;
       }
     }
-    const uint32_t d = eliminate<N, GL>(a, p, pinv, one);
-    if (valid && t == 0) detv[(int64_t)prime * N0 * R + (int64_t)j0 * R + r0 + q] = d;
+    const DetFrac d = eliminate<N, GL>(a, p, pinv, one);
+    if (valid && t == 0) {
+      const int64_t o = (int64_t)prime * N0 * R + (int64_t)j0 * R + r0 + q;
+      detv[o] = d.num;
+      denv[o] = d.den;
+    }
   }
 }
 
 template <int N, int GL>
 __global__ __launch_bounds__(kDetBlock) void det_fused_kernel(
-    const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, int64_t R, int N0, int m0,
-    int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
+    const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
+    int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
     const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
   extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
-  det_fused_body<N, GL>(tile, pre, detv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero, blockIdx.y,
-                        blockIdx.x);
+  det_fused_body<N, GL>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
+                        blockIdx.y, blockIdx.x);
 }
 
 // Batched form: blocks walk the virtual blocks of every matrix of this order in the launch;
@@ -256,19 +274,20 @@ __global__ __launch_bounds__(kDetBlock) void det_fused_batch_kernel(
     const int64_t per_prime = d.rtiles * d.jtiles;
     const int prime = (int)(local / per_prime);
     det_fused_body<N, GL>(tile, (const uint32_t*)(ws + d.pre_off), (uint32_t*)(ws + d.detv_off),
-                          d.R, d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride, d.pc, d.zero, prime,
+                          (uint32_t*)(ws + d.den_off), d.R, d.N0, d.m0, d.Q, d.S, d.tw0,
+                          d.tw_stride, d.pc, d.zero, prime,
                           local - (int64_t)prime * per_prime);
     __syncthreads();  // the next virtual block refills the tile
   }
 }
 
 template <int N, int GL>
-hipError_t det_launch(const uint32_t* eval, uint32_t* detv, int64_t npts, int pn,
+hipError_t det_launch(const uint32_t* eval, uint32_t* detv, uint32_t* denv, int64_t npts, int pn,
                       const PrimeConst* pcs, hipStream_t st) {
   constexpr int per_block = kDetBlock / GL;
   const int64_t bx = (npts + per_block - 1) / per_block;
   hipLaunchKernelGGL((det_kernel<N, GL>), dim3((unsigned)bx, (unsigned)pn), dim3(kDetBlock), 0, st,
-                     eval, detv, npts, pcs);
+                     eval, detv, denv, npts, pcs);
   return hipGetLastError();
 }
 
@@ -287,7 +306,7 @@ hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st) {
   const int64_t jtiles = (f.N0 + f.S - 1) / f.S;
   const size_t lds = (size_t)((N * N) | 1) * f.m0 * f.Q * sizeof(uint32_t);
   hipLaunchKernelGGL((det_fused_kernel<N, GL>), dim3((unsigned)(rtiles * jtiles), (unsigned)f.pn),
-                     dim3(kDetBlock), lds, st, f.pre, f.detv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0,
+                     dim3(kDetBlock), lds, st, f.pre, f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0,
                      f.tw_stride, f.pcs, f.zero);
   return hipGetLastError();
 }

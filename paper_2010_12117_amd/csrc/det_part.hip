@@ -9,8 +9,8 @@
 namespace pd {
 
 #define PD_DET(N, GL)                                                                  \
-  template hipError_t det_launch<N, GL>(const uint32_t*, uint32_t*, int64_t, int,     \
-                                        const PrimeConst*, hipStream_t);              \
+  template hipError_t det_launch<N, GL>(const uint32_t*, uint32_t*, uint32_t*, int64_t,  \
+                                        int, const PrimeConst*, hipStream_t);         \
   template hipError_t det_fused_launch<N, GL>(const FusedDetArgs&, hipStream_t);          \
   template hipError_t det_fused_batch_launch<N, GL>(const BDet*, int, int64_t, size_t,    \
                                                     uint8_t*, hipStream_t);

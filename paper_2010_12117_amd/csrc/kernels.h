@@ -16,6 +16,7 @@ bool det_config_supported(int n, int lanes);
 // Launch shapes shared by the single and the batched paths.
 int expand_outputs_per_thread(int Nv, int64_t inner);
 int intt_lines_per_block(int64_t lines, int Nv, int pn);
+int64_t finalize_threads(int64_t G, int pn);  // threads of the det = num / den launch
 
 hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st);
 hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st);

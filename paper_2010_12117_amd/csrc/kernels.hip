@@ -155,6 +155,60 @@ __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __r
 }
 
 // ------------------------------------------------------------------------------------
+// S3 (end): det = num / den at every point. A thread takes kFinalPoints consecutive points
+// of one prime and inverts their denominators together (Montgomery's simultaneous
+// inversion: prefix products, one Fermat inverse, then back-substitution), which costs one
+// exponentiation per kFinalPoints points instead of one per point. Every den is nonzero.
+// ------------------------------------------------------------------------------------
+constexpr int kFinalPoints = 8;
+
+__device__ __forceinline__ void finalize_body(uint32_t* __restrict__ detv,
+                                              const uint32_t* __restrict__ denv, int64_t t,
+                                              int64_t G, const PrimeConst* __restrict__ pcs) {
+  const int64_t chunks = (G + kFinalPoints - 1) / kFinalPoints;
+  const int prime = (int)(t / chunks);
+  const int64_t i0 = (t - (int64_t)prime * chunks) * kFinalPoints;
+  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
+  uint32_t* num = detv + (int64_t)prime * G + i0;
+  const uint32_t* den = denv + (int64_t)prime * G + i0;
+  uint32_t d[kFinalPoints], pre[kFinalPoints];
+  uint32_t acc = one;
+#pragma unroll
+  for (int i = 0; i < kFinalPoints; ++i) {
+    d[i] = (i0 + i < G) ? den[i] : one;
+    pre[i] = acc;  // product of the denominators before i
+    acc = mm(acc, d[i], p, pinv);
+  }
+  uint32_t inv = minv(acc, one, p, pinv);  // inverse of the product of all
+#pragma unroll
+  for (int i = kFinalPoints - 1; i >= 0; --i) {
+    const uint32_t di = mm(inv, pre[i], p, pinv);  // 1 / d[i]
+    inv = mm(inv, d[i], p, pinv);                   // 1 / (d[0] .. d[i-1])
+    if (i0 + i < G) num[i] = mm(num[i], di, p, pinv);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void finalize_kernel(uint32_t* __restrict__ detv,
+                                                          const uint32_t* __restrict__ denv,
+                                                          int64_t G, int pn,
+                                                          const PrimeConst* __restrict__ pcs) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < (int64_t)pn * ((G + kFinalPoints - 1) / kFinalPoints)) finalize_body(detv, denv, t, G, pcs);
+}
+
+__global__ __launch_bounds__(kBlock) void finalize_batch_kernel(const BFinal* __restrict__ desc,
+                                                                int ndesc, int64_t vblocks,
+                                                                uint8_t* __restrict__ ws) {
+  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
+    const BFinal& d = desc[find_desc(desc, ndesc, vb)];
+    const int64_t t = (vb - d.block0) * kBlock + threadIdx.x;
+    if (t < (int64_t)d.pn * ((d.G + kFinalPoints - 1) / kFinalPoints)) {
+      finalize_body((uint32_t*)(ws + d.detv_off), (const uint32_t*)(ws + d.den_off), t, d.G, d.pc);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // S4: interpolation along one variable (inverse DFT: opposite sign in the exponent; the
 // 1/N factor is applied once in the reconstruction). A block loads a tile of W lines of
 // length Nv into LDS in bit-reversed order, runs log2 Nv radix-2 decimation-in-time stages
@@ -399,10 +453,14 @@ hipError_t launch_expand(const MatPlan& P, const uint32_t* in, uint32_t* out, in
 
 template <int N, int GL>
 hipError_t launch_det_ng(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hipStream_t st) {
-  if (!P.fused) return det_launch<N, GL>((const uint32_t*)(ws + P.off_eval), detv, P.G, P.pn, P.d_pc, st);
+  uint32_t* denv = (uint32_t*)(ws + P.off_den);
+  if (!P.fused) {
+    return det_launch<N, GL>((const uint32_t*)(ws + P.off_eval), detv, denv, P.G, P.pn, P.d_pc, st);
+  }
   FusedDetArgs f;
   f.pre = (const uint32_t*)(ws + P.off_pre);
   f.detv = detv;
+  f.denv = denv;
   f.R = P.G / P.N[0];
   f.N0 = P.N[0];
   f.m0 = P.m[0];
@@ -539,9 +597,18 @@ hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
   return hipSuccess;
 }
 
+int64_t finalize_threads(int64_t G, int pn) {
+  return (int64_t)pn * ((G + kFinalPoints - 1) / kFinalPoints);
+}
+
 hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st) {
-  return det_dispatch<SingleDet>(P.n, P.det_lanes, P, (const uint8_t*)ws,
-                                 (uint32_t*)(ws + P.off_detv), st);
+  hipError_t e = det_dispatch<SingleDet>(P.n, P.det_lanes, P, (const uint8_t*)ws,
+                                         (uint32_t*)(ws + P.off_detv), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(finalize_threads(P.G, P.pn))), dim3(kBlock),
+                     0, st, (uint32_t*)(ws + P.off_detv), (const uint32_t*)(ws + P.off_den), P.G,
+                     P.pn, P.d_pc);
+  return hipGetLastError();
 }
 
 hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
@@ -592,6 +659,13 @@ hipError_t batch_reduce(const BReduce* desc, int ndesc, int64_t vblocks, const i
 hipError_t batch_expand(const BExpand* desc, int ndesc, int64_t vblocks, uint8_t* ws,
                         hipStream_t st) {
   hipLaunchKernelGGL(expand_batch_kernel, dim3(persistent_grid(vblocks)), dim3(kBlock), 0, st,
+                     desc, ndesc, vblocks, ws);
+  return hipGetLastError();
+}
+
+hipError_t batch_final(const BFinal* desc, int ndesc, int64_t vblocks, uint8_t* ws,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(finalize_batch_kernel, dim3(persistent_grid(vblocks)), dim3(kBlock), 0, st,
                      desc, ndesc, vblocks, ws);
   return hipGetLastError();
 }

@@ -342,6 +342,7 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     P.off_eval = s.k == 0 ? P.off_res : take(pn * P.nent * P.G * 4);
   }
   P.off_detv = take(pn * P.G * 4);
+  P.off_den = take(pn * P.G * 4);
   // interpolation passes run over the first variable first, trimming N_v to D_v + 1
   size_t iinter = 0;
   for (int v = 0; v + 1 < s.k; ++v) {

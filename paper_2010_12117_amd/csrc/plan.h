@@ -58,7 +58,8 @@ struct MatPlan {
   size_t off_pre = 0;  // [pn][n*n][m0][R] input of the fused kernel
 
   // workspace layout (bytes, 256-aligned)
-  size_t off_res = 0, off_tmpA = 0, off_tmpB = 0, off_eval = 0, off_detv = 0, off_coef = 0,
+  size_t off_res = 0, off_tmpA = 0, off_tmpB = 0, off_eval = 0, off_detv = 0, off_den = 0,
+         off_coef = 0,
          off_iA = 0, off_iB = 0, ws_bytes = 0;
   size_t in_bytes = 0, out_bytes = 0;
 };

@@ -326,6 +326,9 @@ static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
       case pd::BLaunch::kDet:
         e = pd::batch_det(L.n, L.lanes, (const pd::BDet*)desc, L.ndesc, L.vblocks, L.lds, ws, st);
         break;
+      case pd::BLaunch::kFinal:
+        e = pd::batch_final((const pd::BFinal*)desc, L.ndesc, L.vblocks, ws, st);
+        break;
       case pd::BLaunch::kIntt:
         e = pd::batch_intt((const pd::BIntt*)desc, L.ndesc, L.vblocks, L.lds, ws, st);
         break;

@@ -1,0 +1,200 @@
+"""Continuous-batching request loop for exact polynomial determinants on one GPU.
+
+Clients call `Server.submit(coeffs)` and get a future. A background thread admits queued
+jobs as soon as a stream slot and enough device memory are free, so jobs that arrive while
+others run are started at once and overlap on the device (one HIP stream per admitted job,
+all at the default priority). A job's device footprint is known from its plan before it
+runs: coefficients + workspace (residues, evaluation passes, determinants, interpolation)
++ output limbs. Every intermediate stays on the device; only the input coefficients go in
+and the result limbs come out.
+
+Admission is first come, first served with reservation: when the oldest waiting job does
+not fit, its memory is reserved, and younger jobs may start only if they fit beside that
+reservation. Large jobs therefore cannot starve while small ones keep flowing.
+
+The solve itself is `polydet_solve` (binding.py); this module only schedules it.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+from typing import Deque, List, Optional
+
+import numpy as np
+
+from . import binding as B
+
+
+@dataclass
+class Result:
+    """Limbs (ncoeff x limbs, uint32 two's complement) and plan information of a job."""
+    limbs: np.ndarray
+    info: dict
+    submitted: float
+    started: float
+    finished: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.submitted
+
+    def coefficients(self) -> np.ndarray:
+        """Object array of Python ints with shape (D1+1, ..., Dk+1)."""
+        vals = B.limbs_to_ints(self.limbs)
+        out = np.empty(len(vals), dtype=object)
+        for i, v in enumerate(vals):
+            out[i] = v
+        box = tuple(d + 1 for d in self.info["D"])
+        return out.reshape(box) if box else out.reshape(())
+
+
+@dataclass
+class _Job:
+    coeffs: np.ndarray
+    plan: B.Plan
+    footprint: int
+    future: Future
+    submitted: float
+    started: float = 0.0
+    stream: object = None
+    buffers: tuple = ()
+    host_out: object = None
+    done_event: object = None
+
+
+class Server:
+    """Admits determinant jobs by device memory footprint and runs them concurrently.
+
+    memory_budget: device bytes the server may hold for jobs at once.
+    slots: jobs in flight at once (one stream each)."""
+
+    def __init__(self, memory_budget: int = 64 << 30, slots: int = 4, device: str = "cuda:0",
+                 flags: int = 0):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.budget = int(memory_budget)
+        self.flags = flags
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        self.free_streams = list(range(slots))
+        self.queue: Deque[_Job] = collections.deque()
+        self.running: List[_Job] = []
+        self.in_use = 0
+        self.lock = threading.Condition()
+        self.closed = False
+        self.latencies: List[float] = []
+        self.completed = 0
+        self.thread = threading.Thread(target=self._loop, name="polydet-server", daemon=True)
+        self.thread.start()
+
+    # ------------------------------------------------------------------ client side
+    def submit(self, coeffs: np.ndarray) -> Future:
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.int64)
+        n, deg = B.shape_of(coeffs)
+        pl = B.plan(n, deg, host_coeffs=coeffs, flags=self.flags)
+        info = pl.info
+        footprint = int(info["in_bytes"] + info["workspace_bytes"] + info["out_bytes"])
+        if footprint > self.budget:
+            raise ValueError(f"job needs {footprint} device bytes, above the server budget")
+        fut: Future = Future()
+        job = _Job(coeffs, pl, footprint, fut, time.perf_counter())
+        with self.lock:
+            if self.closed:
+                raise RuntimeError("server is closed")
+            self.queue.append(job)
+            self.lock.notify()
+        return fut
+
+    def close(self, wait: bool = True):
+        with self.lock:
+            self.closed = True
+            self.lock.notify()
+        if wait:
+            self.thread.join()
+
+    def stats(self) -> dict:
+        lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        return {"completed": self.completed, "p50_s": float(np.percentile(lat, 50)),
+                "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean())}
+
+    # ------------------------------------------------------------------ server side
+    def _admit(self):
+        """Start every queued job that fits (called with the lock held)."""
+        reserved = 0
+        kept: Deque[_Job] = collections.deque()
+        while self.queue:
+            job = self.queue.popleft()
+            if self.free_streams and self.in_use + reserved + job.footprint <= self.budget:
+                self._start(job)
+            else:
+                if not kept:
+                    reserved += job.footprint  # the oldest waiting job holds its share
+                kept.append(job)
+        self.queue = kept
+
+    def _start(self, job: _Job):
+        torch = self.torch
+        sid = self.free_streams.pop()
+        stream = self.streams[sid]
+        info = job.plan.info
+        job.started = time.perf_counter()
+        job.stream = sid
+        self.in_use += job.footprint
+        with torch.cuda.stream(stream):
+            host_in = torch.from_numpy(job.coeffs.reshape(-1)).pin_memory()
+            d_in = torch.empty(host_in.numel(), dtype=torch.int64, device=self.device)
+            d_in.copy_(host_in, non_blocking=True)
+            d_out = torch.empty((info["ncoeff"], info["limbs"]), dtype=torch.int32,
+                                device=self.device)
+            ws = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device=self.device)
+            B.solve_device(job.plan, d_in, d_out, ws, stream=stream)
+            job.host_out = torch.empty(d_out.shape, dtype=torch.int32, pin_memory=True)
+            job.host_out.copy_(d_out, non_blocking=True)
+            job.done_event = torch.cuda.Event()
+            job.done_event.record(stream)
+        job.buffers = (host_in, d_in, d_out, ws)
+        self.running.append(job)
+
+    def _finish(self, job: _Job):
+        now = time.perf_counter()
+        info = job.plan.info
+        res = Result(job.host_out.numpy().copy(), info, job.submitted, job.started, now)
+        # the buffers were used on the job's stream only, and that stream is done
+        job.buffers = ()
+        job.host_out = None
+        self.in_use -= job.footprint
+        self.free_streams.append(job.stream)
+        self.latencies.append(res.latency)
+        self.completed += 1
+        job.future.set_result(res)
+
+    def _loop(self):
+        while True:
+            with self.lock:
+                done = [j for j in self.running if j.done_event.query()]
+                for j in done:
+                    self.running.remove(j)
+                for j in done:
+                    try:
+                        self._finish(j)
+                    except Exception as e:  # pragma: no cover - surfaced to the client
+                        j.future.set_exception(e)
+                try:
+                    self._admit()
+                except Exception as e:  # pragma: no cover
+                    while self.queue:
+                        self.queue.popleft().future.set_exception(e)
+                if self.closed and not self.queue and not self.running:
+                    return
+                if not self.running and not self.queue:
+                    self.lock.wait(timeout=0.05)
+            if self.running:
+                time.sleep(0.0002)
+
+
+def poisson_arrivals(rng: np.random.Generator, count: int, rate: float) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson stream with the given rate."""
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))

@@ -1,0 +1,60 @@
+"""The serving loop: jobs admitted by device memory footprint, running concurrently on
+several streams, give results bit-identical to the same job solved alone, and to the
+oracle."""
+import numpy as np
+import pytest
+
+import paper_2010_12117_amd as pdm
+from paper_2010_12117_amd import binding as B
+from paper_2010_12117_amd import serving as S
+import workloads as W
+from oracle import det as OD
+from oracle import plan as PL
+
+from helpers import box_to_dict
+
+pytestmark = pytest.mark.gpu
+
+
+def small_jobs(seed, count):
+    rng = np.random.default_rng(900 + seed)
+    jobs = []
+    for _ in range(count):
+        n = int(rng.integers(2, 11))
+        k = int(rng.integers(2, 4))
+        deg = tuple(int(x) for x in rng.integers(1, 3, size=k))
+        jobs.append(W.random_matrix(rng, n, deg, -65536, 65536))
+    return jobs
+
+
+def alone(a):
+    import torch
+    n, deg = B.shape_of(a)
+    pl = pdm.plan(n, deg, host_coeffs=a)
+    out, _ = pdm.solve_device(pl, torch.from_numpy(np.ascontiguousarray(a)).cuda())
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("budget_mb,slots", [(4096, 4), (48, 2)])
+def test_mix_equals_alone(budget_mb, slots):
+    jobs = small_jobs(budget_mb, 24)
+    srv = S.Server(memory_budget=budget_mb << 20, slots=slots)
+    futs = [srv.submit(a) for a in jobs]
+    results = [f.result(timeout=120) for f in futs]
+    srv.close()
+    st = srv.stats()
+    assert st["completed"] == len(jobs) and st["p99_s"] >= st["p50_s"] > 0
+    for a, r in zip(jobs, results):
+        assert np.array_equal(r.limbs, alone(a))
+    for a, r in list(zip(jobs, results))[:4]:
+        n, deg = B.shape_of(a)
+        expect = OD.det_pointwise(a, PL.det_degree_bound_from_shape(n, deg))
+        assert box_to_dict(r.coefficients()) == box_to_dict(expect)
+
+
+def test_oversized_job_is_rejected():
+    srv = S.Server(memory_budget=1 << 20, slots=1)
+    with pytest.raises(ValueError):
+        srv.submit(W.config2())
+    srv.close()
