@@ -180,11 +180,14 @@ def bench_serving(args):
 
     run(0)  # warm-up: plans, kernels, allocator
     torch.cuda.synchronize()
+    print("serving: warm-up done", file=sys.stderr, flush=True)
     cap = run(0)
     capacity = cap["jobs_per_s"]
+    print(f"serving: capacity {capacity:.1f} jobs/s", file=sys.stderr, flush=True)
     out = {"capacity": cap}
     for rho in (0.5, 0.8):
         out[f"rho_{rho}"] = run(rho * capacity)
+        print(f"serving: rho {rho} done", file=sys.stderr, flush=True)
     line = {
         "metric": "serving: p50/p99 latency and throughput of exact determinant jobs, 1 GPU",
         "value": out["rho_0.8"]["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1,
@@ -196,6 +199,17 @@ def bench_serving(args):
         "results": out,
     }
     print(json.dumps(line), flush=True)
+
+
+def det_kernel_name(info):
+    n, lanes = info["n"], info["det_lanes"]
+    m0 = info["deg"][0] + 1 if info["nvars"] else 1
+    paired = 2 <= m0 <= 4  # first-variable points j0, j0 + N0/2 built by two lanes
+    fused = (("det_fused_pair3_kernel" if lanes == 1 else "det_fused_pair_kernel")
+             if paired else "det_fused_kernel") + f"<{n},{lanes}>"
+    if info["det_left_looking"]:
+        return f"det_ll_kernel<{n}> + repair {fused} + finalize_kernel"
+    return f"{fused} + finalize_kernel"
 
 
 def main():
@@ -214,6 +228,8 @@ def main():
                     help="serving: device memory for jobs in flight")
     ap.add_argument("--det-lanes", type=int, default=0,
                     help="lanes per determinant (1, 2, 4, 8, 16); 0 = the plan's choice")
+    ap.add_argument("--det-form", default="auto", choices=["auto", "left-looking", "exchange"],
+                    help="elimination form of the determinant kernel (results are identical)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before the timed loop, copy 1 GiB device to device once (a kernel of "
                          "known traffic for scaling hardware byte counters)")
@@ -241,6 +257,8 @@ def main():
     flags = pdm.STAGE_TIMING
     if args.det_lanes:
         flags |= pdm.DET_LANES_LOG2(args.det_lanes.bit_length() - 1)
+    flags |= {"auto": 0, "left-looking": pdm.DET_LEFT_LOOKING,
+              "exchange": pdm.DET_EXCHANGE}[args.det_form]
     pl = pdm.plan(n, deg, host_coeffs=arr, flags=flags)
     info = pl.info
     pn, G = info["pn"], info["G"]
@@ -287,7 +305,7 @@ def main():
                if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
     det_roof = {"bound": "alu", "achieved": det_achieved, "peak": ALU_PEAK_UPDATES / 1e12,
                 "unit": "T elimination-updates/s", "frac": det_achieved / (ALU_PEAK_UPDATES / 1e12),
-                "traffic": traffic, "kernel": f"det_fused_kernel<{n},{info['det_lanes']}>",
+                "traffic": traffic, "kernel": det_kernel_name(info),
                 "work_per_launch": det_work, "avg_ms": per["determinants"]}
     eval_roof = {"bound": "hbm", "achieved": eval_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": eval_gbs / HBM_PEAK_GBS, "traffic": None,

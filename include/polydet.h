@@ -79,6 +79,14 @@ typedef struct polydet_shape {
  * chunks that fit the workspace; per chunk one persistent launch per stage and one per
  * matrix order for the elimination). Results are identical either way. */
 #define POLYDET_BATCH_PLAIN ((uint32_t)2u)
+/* POLYDET_DET_LEFT_LOOKING / POLYDET_DET_EXCHANGE: choose the elimination form. By default
+ * (and with EXCHANGE) the exchanging kernel computes every determinant. LEFT_LOOKING, for
+ * orders up to 16 when the first variable is evaluated inside the elimination, first runs a
+ * left-looking pass (one lane per matrix, only the pivot rows in registers, no row
+ * exchanges); the points where it meets a zero pivot are then recomputed by the exchanging
+ * kernel. Results are identical either way. */
+#define POLYDET_DET_LEFT_LOOKING ((uint32_t)4u)
+#define POLYDET_DET_EXCHANGE ((uint32_t)8u)
 /* The workspace budget of one chunk of a batched solve is 16 GiB, or the value of the
  * environment variable POLYDET_BATCH_BUDGET_MB (in MiB) read when the plan is made; a single
  * matrix larger than the budget forms a chunk of its own. */
@@ -129,6 +137,7 @@ typedef struct polydet_plan_info {
    * of that matrix is input row row_order[i] (i < n). Stage values at off_eval and off_detv
    * refer to the reordered matrix, whose determinant is det_sign times det M. */
   uint8_t row_order[32];
+  int32_t det_left_looking; /* 1 if a left-looking pass runs before the exchanging kernel */
 } polydet_plan_info;
 
 typedef struct polydet_plan_s* polydet_plan_t;

@@ -5,13 +5,13 @@ kernels for gfx950 behind a C ABI (include/polydet.h); this package is the thin 
 binding (binding.py) and the build script (build.py).
 """
 from .binding import (DET_LANES_LOG2, FORCE_PN, HOST_ONLY, PRIME_OFFSET, STAGE_TIMING, STAGES,
-                      UNFUSED_EVAL, BATCH_PLAIN,
+                      UNFUSED_EVAL, BATCH_PLAIN, DET_LEFT_LOOKING, DET_EXCHANGE,
                       Plan, PolydetError,
                       det, limbs_to_ints, limits, load_library, plan, plan_batch,
                       solve_batch_device, solve_device)
 
 __all__ = ["DET_LANES_LOG2", "FORCE_PN", "HOST_ONLY", "PRIME_OFFSET", "STAGE_TIMING", "STAGES",
-           "UNFUSED_EVAL", "BATCH_PLAIN",
+           "UNFUSED_EVAL", "BATCH_PLAIN", "DET_LEFT_LOOKING", "DET_EXCHANGE",
            "Plan", "PolydetError",
            "det", "limbs_to_ints", "limits", "load_library", "plan", "plan_batch",
            "solve_batch_device", "solve_device"]

@@ -34,6 +34,8 @@ def PRIME_OFFSET(x: int) -> int:
 
 UNFUSED_EVAL = 1
 BATCH_PLAIN = 2
+DET_LEFT_LOOKING = 4
+DET_EXCHANGE = 8
 HOST_ONLY = 1 << 31
 STAGE_TIMING = 1 << 30
 STAGES = ("reduce", "evaluate", "determinants", "interpolate", "reconstruct")
@@ -60,7 +62,7 @@ class PlanInfo(ctypes.Structure):
                 ("in_bytes", ctypes.c_size_t), ("out_bytes", ctypes.c_size_t),
                 ("workspace_bytes", ctypes.c_size_t), ("off_eval", ctypes.c_size_t),
                 ("off_detv", ctypes.c_size_t), ("off_coef", ctypes.c_size_t),
-                ("row_order", ctypes.c_uint8 * 32)]
+                ("row_order", ctypes.c_uint8 * 32), ("det_left_looking", ctypes.c_int32)]
 
 
 EXPORTS = ["polydet_plan", "polydet_plan_batch", "polydet_plan_query", "polydet_plan_primes",

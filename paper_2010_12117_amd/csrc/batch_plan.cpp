@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <tuple>
 
 #include "kernels.h"
 
@@ -182,11 +183,12 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
       L.vblocks = vb;
       B.launches.push_back(L);
     }
-    // S3 elimination with the first variable's evaluation: one launch per (order, lanes)
-    std::map<std::pair<int, int>, std::vector<size_t>> classes;
+    // S3 elimination with the first variable's evaluation: one launch per (order, lanes,
+    // elimination form, paired evaluation)
+    std::map<std::tuple<int, int, int, int>, std::vector<size_t>> classes;
     for (size_t c = 0; c < chunk.size(); ++c) {
       const MatPlan& P = mats[chunk[c]];
-      classes[{-P.n, P.det_lanes}].push_back(c);
+      classes[{-P.n, P.det_lanes, P.det_ll ? 1 : 0, fused_paired(P.m[0]) ? 1 : 0}].push_back(c);
     }
     for (auto& kv : classes) {
       std::vector<BDet> d;
@@ -202,7 +204,7 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         e.R = P.G / P.N[0];
         e.tw_stride = P.tw_stride;
         e.rtiles = (e.R + P.fuse_Q - 1) / P.fuse_Q;
-        e.jtiles = (P.N[0] + P.fuse_S - 1) / P.fuse_S;
+        e.jtiles = (fused_jrange(P.N[0], P.m[0]) + P.fuse_S - 1) / P.fuse_S;
         e.N0 = P.N[0];
         e.m0 = P.m[0];
         e.Q = P.fuse_Q;
@@ -219,9 +221,15 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
       L.desc_off = push(d.data(), d.size() * sizeof(BDet));
       L.ndesc = (int)d.size();
       L.vblocks = vb;
-      L.n = -kv.first.first;
-      L.lanes = kv.first.second;
+      L.n = -std::get<0>(kv.first);
+      L.lanes = std::get<1>(kv.first);
+      L.pair = std::get<3>(kv.first);
       L.lds = lds;
+      if (std::get<2>(kv.first)) {
+        L.ll = 1;  // left-looking pass, then the repair pass of the exchanging kernel
+        B.launches.push_back(L);
+        L.ll = 2;
+      }
       B.launches.push_back(L);
     }
     // S3 end: det = num / den for every matrix of the chunk, one launch

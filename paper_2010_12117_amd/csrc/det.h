@@ -22,10 +22,16 @@ struct FusedDetArgs {
   const PrimeConst* pcs;
   const uint8_t* zero;   // [n*n] zero-entry flags or null
   int pn;
+  bool fixup;            // repair launch: recompute only the points with den = 0
 };
 
 template <int N, int GL>
 hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st);
+
+// Left-looking form, one lane per matrix (det_impl.h, det_ll_kernel); points with a zero
+// pivot are left with den = 0 for a repair launch of det_fused_launch with fixup = true.
+template <int N>
+hipError_t det_ll_launch(const FusedDetArgs& f, hipStream_t st);
 
 template <int N, int GL>
 hipError_t det_launch(const uint32_t* eval, uint32_t* detv, uint32_t* denv, int64_t npts, int pn,

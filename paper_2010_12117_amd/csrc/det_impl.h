@@ -7,6 +7,7 @@
 #include "batch.h"
 #include "det.h"
 #include "modarith.h"
+#include "plan.h"
 
 namespace pd {
 
@@ -138,31 +139,16 @@ __global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restri
   }
 }
 
-// Fused form: the last evaluation axis (the first variable, whose grid index j0 is the
-// slowest) runs inside the elimination kernel, so the full evaluation tensor never exists.
-// pre[pn][n*n][m0][R] holds every entry already evaluated along the other variables (R
-// points) with its m0 coefficients in the first variable. A block stages the columns
-// r0 .. r0+Q-1 of every nonzero entry in LDS as tile[m][q][e] (row stride NEP = n*n | 1, odd,
-// so lanes reading different q hit different banks and the entry index is an immediate
-// offset) and then, for S values of j0, each lane group rebuilds its matrix at the point
-// (j0, r0 + q) by Horner's rule in w0^j0 (the evaluation of Section 2 along x1) and
-// eliminates it. Point index = j0 R + r.
-// One block's share of the fused kernel: prime `prime`, tile `bx` = (j-range, r-range).
-template <int N, int GL>
-__device__ __forceinline__ void det_fused_body(
-    uint32_t* tile, const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv,
-    uint32_t* __restrict__ denv, int64_t R,
-    int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, int prime, int64_t bx) {
-  constexpr int C = (N + GL - 1) / GL;
+// Stages columns r0 .. r0+Q-1 of the pre-tensor pre[n*n][m0][R] (one prime) in LDS as
+// tile[m][q][e] with row stride NEP = n*n | 1 (odd, so lanes reading different q hit
+// different banks, and the entry index e is an immediate offset). Zero entries and columns
+// past R are stored as zeros without reading memory.
+template <int N>
+__device__ __forceinline__ void fill_tile(uint32_t* tile, const uint32_t* __restrict__ src,
+                                          int64_t R, int m0, int Q, int64_t r0,
+                                          const uint8_t* __restrict__ zero) {
   constexpr int NE = N * N;
   constexpr int NEP = NE | 1;
-  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
-  const int64_t rtiles = (R + Q - 1) / Q;
-  const int64_t r0 = (bx % rtiles) * Q;
-  const int jbase = (int)(bx / rtiles) * S;
-  const uint32_t* src = pre + (int64_t)prime * NE * m0 * R;
-
   const int mq = m0 * Q;
   for (int idx = threadIdx.x; idx < NE * mq; idx += kDetBlock) {
     const int e = idx / mq;
@@ -173,12 +159,70 @@ __device__ __forceinline__ void det_fused_body(
     if (!(zero && zero[e]) && r0 + q < R) v = src[((int64_t)e * m0 + m) * R + r0 + q];
     tile[rem * NEP + e] = v;
   }
+}
+
+// In a repair launch (fixup = true) a block recomputes only the points whose denominator an
+// earlier launch left at 0 (a zero pivot the left-looking kernel cannot exchange away).
+// Returns whether this block has such a point; every thread of the block gets the answer.
+__device__ __forceinline__ bool block_needs_fixup(const uint32_t* __restrict__ denv, int64_t R,
+                                                  int N0, int NJ, int Q, int S, int64_t r0,
+                                                  int jbase, int prime) {
+  int any = 0;
+  const int halves = N0 / NJ;  // 2 when the points j0 and j0 + N0/2 are taken in pairs
+  const int pts = Q * S * halves;
+  for (int idx = threadIdx.x; idx < pts; idx += kDetBlock) {
+    const int q = idx % Q, jo = (idx / Q) % S, hh = idx / (Q * S);
+    const int j0 = jbase + jo;
+    if (r0 + q < R && j0 < NJ &&
+        denv[(int64_t)prime * N0 * R + (int64_t)(j0 + hh * NJ) * R + r0 + q] == 0u)
+      any = 1;
+  }
+  return __syncthreads_or(any) != 0;
+}
+
+// Fused form: the last evaluation axis (the first variable, whose grid index j0 is the
+// slowest) runs inside the elimination kernel, so the full evaluation tensor never exists.
+// pre[pn][n*n][m0][R] holds every entry already evaluated along the other variables (R
+// points) with its m0 coefficients in the first variable. A block stages the columns
+// r0 .. r0+Q-1 in LDS (fill_tile) and then, for S values of j0, each lane group rebuilds its
+// matrix at the point (j0, r0 + q) as sum_m x_m w0^{m j0} (the evaluation of Section 2 along
+// x1) and eliminates it with row exchanges. Point index = j0 R + r.
+//
+// PAIR (2 <= m0 <= 4, fused_paired): j0 runs over [0, N0/2) and lanes l and l + 32 of a wave
+// build the points j0 and j0 + N0/2 of the same (slot, r) together. The lower lane sums the
+// even terms E = x0 + x2 w0^{2 j0}, the upper one the odd terms O = x1 w0^{j0} + x3 w0^{3 j0}
+// (one reduction each), they exchange the sums, and since w0^{N0/2} = -1 the values are
+// E + O and E - O: half the products and LDS reads of the unpaired form.
+// One block's share of the fused kernel: prime `prime`, tile `bx` = (j-range, r-range).
+template <int N, int GL, bool PAIR>
+__device__ __forceinline__ void det_fused_body(
+    uint32_t* tile, const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv,
+    uint32_t* __restrict__ denv, int64_t R,
+    int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, int prime, int64_t bx,
+    bool fixup) {
+  constexpr int C = (N + GL - 1) / GL;
+  constexpr int NE = N * N;
+  constexpr int NEP = NE | 1;
+  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
+  const int64_t rtiles = (R + Q - 1) / Q;
+  const int64_t r0 = (bx % rtiles) * Q;
+  const int jbase = (int)(bx / rtiles) * S;
+  const uint32_t* src = pre + (int64_t)prime * NE * m0 * R;
+  const int NJ = PAIR ? N0 / 2 : N0;
+  if (fixup && !block_needs_fixup(denv, R, N0, NJ, Q, S, r0, jbase, prime)) return;
+  fill_tile<N>(tile, src, R, m0, Q, r0, zero);
   __syncthreads();
 
-  const int t = (int)(threadIdx.x % GL);
-  const int slot = (int)(threadIdx.x / GL);
+  // lane -> (half, pair index): lanes l and l + 32 of a wave share (slot, r, j0) when paired
+  const int lane = (int)(threadIdx.x & 63);
+  const int half = PAIR ? (lane >> 5) : 0;
+  const int pidx = PAIR ? (int)(((threadIdx.x >> 6) << 5) | (unsigned)(lane & 31))
+                        : (int)threadIdx.x;
+  const int t = pidx % GL;
+  const int slot = pidx / GL;
   const int q = slot % Q;
-  const int J = (kDetBlock / GL) / Q;
+  const int J = ((PAIR ? kDetBlock / 2 : kDetBlock) / GL) / Q;
   const int jj = slot / Q;
   const bool qvalid = r0 + q < R;
   const uint32_t* w0 = tw0 + (int64_t)prime * tw_stride;
@@ -187,53 +231,75 @@ __device__ __forceinline__ void det_fused_body(
   const int tl = t < N - (C - 1) * GL ? t : N - 1 - (C - 1) * GL;
   const int dl = tl - t;
 
-  for (int j = jbase; j < jbase + S && j < N0; j += J) {
+  for (int j = jbase; j < jbase + S && j < NJ; j += J) {
     const int j0 = j + jj;
-    const bool valid = qvalid && j0 < N0 && j0 < jbase + S;
-    const int j0c = j0 < N0 ? j0 : N0 - 1;
+    const bool valid = qvalid && j0 < NJ && j0 < jbase + S;
+    const int j0c = j0 < NJ ? j0 : NJ - 1;
     uint32_t a[C][N];
-    // a[c][i] = sum_{m < m0} x_m w0^{m j0}, two terms per reduction (mm2). With m0 even the
-    // constant term pairs with x_1 (its factor is R mod p, the representative of 1); with
-    // m0 odd it stands alone. The loop over m is uniform and sits outside the unrolled
-    // loops over the entries held by the lane.
-    int mstart;
-    if ((m0 & 1) == 0) {
-      const uint32_t w1 = w0[j0c & (N0 - 1)];
-      const uint32_t* r0w = tile + q * NEP + t;
-      const uint32_t* r1w = r0w + Q * NEP;
+    if constexpr (PAIR) {
+      // terms m = half and m = half + 2 of every entry, weight w0^{m j0} (0 past m0 - 1,
+      // where the row index is clamped to a valid row); w0^0 is the representative of 1
+      const int ma = half, mb = half + 2;
+      const uint32_t wa = ma < m0 ? w0[(ma * j0c) & (N0 - 1)] : 0u;
+      const uint32_t wb = mb < m0 ? w0[(mb * j0c) & (N0 - 1)] : 0u;
+      const uint32_t* ra = tile + ((ma < m0 ? ma : m0 - 1) * Q + q) * NEP + t;
+      const uint32_t* rb = tile + ((mb < m0 ? mb : m0 - 1) * Q + q) * NEP + t;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
           const int off = i * N + c * GL + (c == C - 1 ? dl : 0);
-          a[c][i] = mm2(r0w[off], one, r1w[off], w1, p, pinv);
+          const uint32_t v = mm2(ra[off], wa, rb[off], wb, p, pinv);
+          // afterwards every lane holds E (the lower lane's v) and O (the upper lane's v)
+          const auto eo = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+          a[c][i] = fold(eo[0] + (half ? p - eo[1] : eo[1]), p);
           if ((c * N + i) % kEvalChunk == kEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
         }
       }
-      mstart = 2;
     } else {
-      const uint32_t* r0w = tile + q * NEP + t;
+      // a[c][i] = sum_{m < m0} x_m w0^{m j0}, two terms per reduction (mm2). With m0 even
+      // the constant term pairs with x_1 (its factor is R mod p, the representative of 1);
+      // with m0 odd it stands alone. The loop over m is uniform and sits outside the
+      // unrolled loops over the entries held by the lane.
+      int mstart;
+      if ((m0 & 1) == 0) {
+        const uint32_t w1 = w0[j0c & (N0 - 1)];
+        const uint32_t* r0w = tile + q * NEP + t;
+        const uint32_t* r1w = r0w + Q * NEP;
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
+        for (int c = 0; c < C; ++c) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) a[c][i] = r0w[i * N + c * GL + (c == C - 1 ? dl : 0)];
+          for (int i = 0; i < N; ++i) {
+            const int off = i * N + c * GL + (c == C - 1 ? dl : 0);
+            a[c][i] = mm2(r0w[off], one, r1w[off], w1, p, pinv);
+            if ((c * N + i) % kEvalChunk == kEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        mstart = 2;
+      } else {
+        const uint32_t* r0w = tile + q * NEP + t;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) a[c][i] = r0w[i * N + c * GL + (c == C - 1 ? dl : 0)];
+        }
+        mstart = 1;
       }
-      mstart = 1;
-    }
-    for (int m = mstart; m < m0; m += 2) {
-      const uint32_t wa = w0[(m * j0c) & (N0 - 1)];
-      const uint32_t wb = w0[((m + 1) * j0c) & (N0 - 1)];
-      const uint32_t* ra = tile + (m * Q + q) * NEP + t;
-      const uint32_t* rb = ra + Q * NEP;
+      for (int m = mstart; m < m0; m += 2) {
+        const uint32_t wa = w0[(m * j0c) & (N0 - 1)];
+        const uint32_t wb = w0[((m + 1) * j0c) & (N0 - 1)];
+        const uint32_t* ra = tile + (m * Q + q) * NEP + t;
+        const uint32_t* rb = ra + Q * NEP;
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
+        for (int c = 0; c < C; ++c) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-          const int off = i * N + c * GL + (c == C - 1 ? dl : 0);
-          a[c][i] = addm(a[c][i], mm2(ra[off], wa, rb[off], wb, p, pinv), p);
-          // bound the scheduler's window so that the LDS reads (one register each) are
-          // not all hoisted ahead of the arithmetic
-          if ((c * N + i) % kEvalChunk == kEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
+          for (int i = 0; i < N; ++i) {
+            const int off = i * N + c * GL + (c == C - 1 ? dl : 0);
+            a[c][i] = addm(a[c][i], mm2(ra[off], wa, rb[off], wb, p, pinv), p);
+            // bound the scheduler's window so that the LDS reads (one register each) are
+            // not all hoisted ahead of the arithmetic
+            if ((c * N + i) % kEvalChunk == kEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
+          }
         }
       }
     }
@@ -244,8 +310,8 @@ __device__ __forceinline__ void det_fused_body(
       }
     }
     const DetFrac d = eliminate<N, GL>(a, p, pinv, one);
-    if (valid && t == 0) {
-      const int64_t o = (int64_t)prime * N0 * R + (int64_t)j0 * R + r0 + q;
+    const int64_t o = (int64_t)prime * N0 * R + (int64_t)(j0 + half * NJ) * R + r0 + q;
+    if (valid && t == 0 && (!fixup || denv[o] == 0u)) {
       detv[o] = d.num;
       denv[o] = d.den;
     }
@@ -256,16 +322,227 @@ template <int N, int GL>
 __global__ __launch_bounds__(kDetBlock) void det_fused_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
     int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, bool fixup) {
   extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
-  det_fused_body<N, GL>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
-                        blockIdx.y, blockIdx.x);
+  det_fused_body<N, GL, false>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs,
+                               zero, blockIdx.y, blockIdx.x, fixup);
+}
+
+template <int N, int GL>
+__global__ __launch_bounds__(kDetBlock) void det_fused_pair_kernel(
+    const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
+    int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, bool fixup) {
+  extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
+  det_fused_body<N, GL, true>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs,
+                              zero, blockIdx.y, blockIdx.x, fixup);
+}
+
+// The same, held to three waves per SIMD. With one lane per matrix the compiler lands just
+// above 168 registers at n = 12 (two waves); at 168 it needs no spills. Used for lanes = 1.
+template <int N, int GL>
+__global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(3)))
+void det_fused_pair3_kernel(
+    const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
+    int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, bool fixup) {
+  extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
+  det_fused_body<N, GL, true>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs,
+                              zero, blockIdx.y, blockIdx.x, fixup);
 }
 
 // Batched form: blocks walk the virtual blocks of every matrix of this order in the launch;
 // virtual block vb of matrix d is (prime, tile) = divmod(vb - block0, rtiles * jtiles).
+template <int N, int GL, bool PAIR>
+__device__ __forceinline__ void det_fused_batch_body(uint32_t* tile, const BDet* __restrict__ desc,
+                                                     int ndesc, int64_t vblocks,
+                                                     uint8_t* __restrict__ ws, bool fixup) {
+  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
+    const BDet& d = desc[find_desc(desc, ndesc, vb)];
+    const int64_t local = vb - d.block0;
+    const int64_t per_prime = d.rtiles * d.jtiles;
+    const int prime = (int)(local / per_prime);
+    det_fused_body<N, GL, PAIR>(tile, (const uint32_t*)(ws + d.pre_off),
+                                (uint32_t*)(ws + d.detv_off), (uint32_t*)(ws + d.den_off), d.R,
+                                d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride, d.pc, d.zero, prime,
+                                local - (int64_t)prime * per_prime, fixup);
+    __syncthreads();  // the next virtual block refills the tile
+  }
+}
+
 template <int N, int GL>
 __global__ __launch_bounds__(kDetBlock) void det_fused_batch_kernel(
+    const BDet* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws,
+    bool fixup) {
+  extern __shared__ uint32_t tile[];
+  det_fused_batch_body<N, GL, false>(tile, desc, ndesc, vblocks, ws, fixup);
+}
+
+template <int N, int GL>
+__global__ __launch_bounds__(kDetBlock) void det_fused_pair_batch_kernel(const BDet* __restrict__ desc, int ndesc, int64_t vblocks,
+                                 uint8_t* __restrict__ ws, bool fixup) {
+  extern __shared__ uint32_t tile[];
+  det_fused_batch_body<N, GL, true>(tile, desc, ndesc, vblocks, ws, fixup);
+}
+
+// ------------------------------------------------------------------------------------
+// Left-looking form of the same condensation, one lane per matrix. Row i is evaluated from
+// the LDS tile when it is needed and reduced against the stored pivot rows k < i in order,
+//   r[c] <- pi_k r[c] - r[k] U[k][c]   (c > k),
+// which are exactly the updates the right-looking form applies to row i at steps 0..i-1, so
+// the pivots and the quotient num / den are the same. Only the pivots pi_k and the strict
+// upper parts U[k][c] stay in registers (n(n+1)/2 - 1 values instead of n^2), which leaves
+// room for four waves per SIMD at n = 12. Rows cannot be exchanged here: a zero pivot (the
+// plan's row order removes the structural ones, so it happens only when a value vanishes
+// mod p) marks the point with den = 0 and the exchanging kernel recomputes it in a repair
+// launch (fixup = true in det_fused_body).
+// ------------------------------------------------------------------------------------
+
+// Columns evaluated between scheduling barriers: the row is evaluated while every earlier
+// pivot row is live, so its loads and 64-bit products are kept to a few at a time.
+constexpr int kLLEvalChunk = 4;
+
+template <int N>
+__device__ __forceinline__ void eval_row(uint32_t (&r)[N], const uint32_t* tile, int i, int q,
+                                         int Q, int m0, const uint32_t* __restrict__ w0, int j0,
+                                         int mask, uint32_t one, uint32_t p, uint32_t pinv) {
+  constexpr int NEP = (N * N) | 1;
+  const uint32_t* b0 = tile + q * NEP + i * N;
+  const int step = Q * NEP;
+  // sum_{m < m0} x_m w^m, two terms per reduction; m0 even pairs the constant term with x_1
+  int m;
+  if ((m0 & 1) == 0) {
+    const uint32_t w1 = w0[j0 & mask];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      r[c] = mm2(b0[c], one, b0[step + c], w1, p, pinv);
+      if (c % kLLEvalChunk == kLLEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    m = 2;
+  } else {
+#pragma unroll
+    for (int c = 0; c < N; ++c) r[c] = b0[c];
+    m = 1;
+  }
+#pragma unroll 1
+  for (; m + 1 < m0; m += 2) {
+    const uint32_t wa = w0[(m * j0) & mask], wb = w0[((m + 1) * j0) & mask];
+    const uint32_t* ra = b0 + m * step;
+    const uint32_t* rb = ra + step;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      r[c] = addm(r[c], mm2(ra[c], wa, rb[c], wb, p, pinv), p);
+      if (c % kLLEvalChunk == kLLEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// Row I of the left-looking pass: evaluate row I at the point, apply the I earlier pivot
+// rows in order (each a Chio step with its pivot), and keep the result as the next pivot row.
+// Recursion over I keeps every register index a compile-time constant.
+template <int N, int I>
+__device__ __forceinline__ void ll_rows(uint32_t (&piv)[N], uint32_t (&U)[N][N], uint32_t& e,
+                                        uint32_t& den, bool& bad, const uint32_t* tile, int q,
+                                        int Q, int m0, const uint32_t* __restrict__ w0, int j0,
+                                        int mask, uint32_t one, uint32_t p, uint32_t pinv) {
+  if constexpr (I < N) {
+    // keep the scheduler from hoisting later rows' LDS reads (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t r[N];
+    eval_row<N>(r, tile, I, q, Q, m0, w0, j0, mask, one, p, pinv);
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+      const uint32_t mk = p - r[k];  // -A[I][k]; p stands for 0
+#pragma unroll
+      for (int c = 0; c < N; ++c)
+        if (c > k) r[c] = mm2(piv[k], r[c], mk, U[k][c], p, pinv);
+    }
+    // Pin the finished row in place: otherwise the compiler sinks each row's elimination
+    // to where its results are first used, behind the evaluation of the later rows, and all
+    // n evaluated rows end up live together.
+#pragma unroll
+    for (int c = I; c < N; ++c) asm volatile("" : "+v"(r[c]));
+    piv[I] = r[I];
+    if constexpr (I < N - 1) {
+      bad = bad || (r[I] == 0u);
+#pragma unroll
+      for (int c = I + 1; c < N; ++c) U[I][c] = r[c];
+      if constexpr (I <= N - 3) {
+        e = mm(e, r[I], p, pinv);
+        den = mm(den, e, p, pinv);
+      }
+    }
+    ll_rows<N, I + 1>(piv, U, e, den, bad, tile, q, Q, m0, w0, j0, mask, one, p, pinv);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void det_ll_body(
+    uint32_t* tile, const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv,
+    uint32_t* __restrict__ denv, int64_t R, int N0, int m0, int Q, int S,
+    const uint32_t* __restrict__ tw0, int64_t tw_stride, const PrimeConst* __restrict__ pcs,
+    const uint8_t* __restrict__ zero, int prime, int64_t bx) {
+  constexpr int NE = N * N;
+  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
+  // The exchanging kernel's tiles (Q points, S values of j0 in [0, N0/2) with their partners
+  // j0 + N0/2 when paired) cover the same points as these: S' = 2 S values of j0 in [0, N0).
+  S = fused_paired(m0) ? 2 * S : S;
+  const int64_t rtiles = (R + Q - 1) / Q;
+  const int64_t r0 = (bx % rtiles) * Q;
+  const int jbase = (int)(bx / rtiles) * S;
+  fill_tile<N>(tile, pre + (int64_t)prime * NE * m0 * R, R, m0, Q, r0, zero);
+  __syncthreads();
+
+  const int q = (int)(threadIdx.x % Q);
+  const int J = kDetBlock / Q;
+  const int jj = (int)(threadIdx.x / Q);
+  const bool qvalid = r0 + q < R;
+  const uint32_t* w0 = tw0 + (int64_t)prime * tw_stride;
+
+  for (int j = jbase; j < jbase + S && j < N0; j += J) {
+    const int j0 = j + jj;
+    const bool valid = qvalid && j0 < N0 && j0 < jbase + S;
+    const int j0c = j0 < N0 ? j0 : N0 - 1;
+    uint32_t piv[N];
+    uint32_t U[N][N];  // U[k][c] for c > k only
+    uint32_t e = one, den = one;
+    bool bad = false;
+    // The tile does not change inside this loop; an opaque copy of its offset keeps the
+    // compiler from hoisting all n^2 constant-term reads out of the loop into registers.
+    int qoff = q;
+    asm volatile("" : "+v"(qoff));
+    ll_rows<N, 0>(piv, U, e, den, bad, tile, qoff, Q, m0, w0, j0c, N0 - 1, one, p, pinv);
+    // Without this the compiler sinks the whole elimination into the store branch below,
+    // after all n rows have been evaluated, and every row is then live at once.
+    uint32_t last = piv[N - 1];
+    asm volatile("" : "+v"(last), "+v"(den));
+    uint32_t num = last;
+    if (bad) {
+      num = 0u;
+      den = 0u;  // repair marker
+    } else if (last == 0u) {
+      den = one;  // singular mod p
+    }
+    if (valid) {
+      const int64_t o = (int64_t)prime * N0 * R + (int64_t)j0 * R + r0 + q;
+      detv[o] = num;
+      denv[o] = den;
+    }
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kDetBlock) void det_ll_kernel(
+    const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
+    int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
+  extern __shared__ uint32_t tile[];
+  det_ll_body<N>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero, blockIdx.y,
+                 blockIdx.x);
+}
+
+template <int N>
+__global__ __launch_bounds__(kDetBlock) void det_ll_batch_kernel(
     const BDet* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws) {
   extern __shared__ uint32_t tile[];
   for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
@@ -273,10 +550,9 @@ __global__ __launch_bounds__(kDetBlock) void det_fused_batch_kernel(
     const int64_t local = vb - d.block0;
     const int64_t per_prime = d.rtiles * d.jtiles;
     const int prime = (int)(local / per_prime);
-    det_fused_body<N, GL>(tile, (const uint32_t*)(ws + d.pre_off), (uint32_t*)(ws + d.detv_off),
-                          (uint32_t*)(ws + d.den_off), d.R, d.N0, d.m0, d.Q, d.S, d.tw0,
-                          d.tw_stride, d.pc, d.zero, prime,
-                          local - (int64_t)prime * per_prime);
+    det_ll_body<N>(tile, (const uint32_t*)(ws + d.pre_off), (uint32_t*)(ws + d.detv_off),
+                   (uint32_t*)(ws + d.den_off), d.R, d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride,
+                   d.pc, d.zero, prime, local - (int64_t)prime * per_prime);
     __syncthreads();  // the next virtual block refills the tile
   }
 }
@@ -293,9 +569,35 @@ hipError_t det_launch(const uint32_t* eval, uint32_t* detv, uint32_t* denv, int6
 
 template <int N, int GL>
 hipError_t det_fused_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
-                                  uint8_t* ws, hipStream_t st) {
+                                  uint8_t* ws, bool pair, bool fixup, hipStream_t st) {
   const int64_t grid = vblocks < kPersistentBlocks ? vblocks : kPersistentBlocks;
-  hipLaunchKernelGGL((det_fused_batch_kernel<N, GL>), dim3((unsigned)(grid < 1 ? 1 : grid)),
+  const dim3 g((unsigned)(grid < 1 ? 1 : grid));
+  if (pair)
+    hipLaunchKernelGGL((det_fused_pair_batch_kernel<N, GL>), g, dim3(kDetBlock), lds, st, desc,
+                       ndesc, vblocks, ws, fixup);
+  else
+    hipLaunchKernelGGL((det_fused_batch_kernel<N, GL>), g, dim3(kDetBlock), lds, st, desc, ndesc,
+                       vblocks, ws, fixup);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t det_ll_launch(const FusedDetArgs& f, hipStream_t st) {
+  const int64_t rtiles = (f.R + f.Q - 1) / f.Q;
+  const int Sl = fused_paired(f.m0) ? 2 * f.S : f.S;
+  const int64_t jtiles = (f.N0 + Sl - 1) / Sl;
+  const size_t lds = (size_t)((N * N) | 1) * f.m0 * f.Q * sizeof(uint32_t);
+  hipLaunchKernelGGL((det_ll_kernel<N>), dim3((unsigned)(rtiles * jtiles), (unsigned)f.pn),
+                     dim3(kDetBlock), lds, st, f.pre, f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S,
+                     f.tw0, f.tw_stride, f.pcs, f.zero);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t det_ll_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
+                               uint8_t* ws, hipStream_t st) {
+  const int64_t grid = vblocks < kPersistentBlocks ? vblocks : kPersistentBlocks;
+  hipLaunchKernelGGL((det_ll_batch_kernel<N>), dim3((unsigned)(grid < 1 ? 1 : grid)),
                      dim3(kDetBlock), lds, st, desc, ndesc, vblocks, ws);
   return hipGetLastError();
 }
@@ -303,11 +605,22 @@ hipError_t det_fused_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, 
 template <int N, int GL>
 hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st) {
   const int64_t rtiles = (f.R + f.Q - 1) / f.Q;
-  const int64_t jtiles = (f.N0 + f.S - 1) / f.S;
+  const int64_t jtiles = (fused_jrange(f.N0, f.m0) + f.S - 1) / f.S;
   const size_t lds = (size_t)((N * N) | 1) * f.m0 * f.Q * sizeof(uint32_t);
-  hipLaunchKernelGGL((det_fused_kernel<N, GL>), dim3((unsigned)(rtiles * jtiles), (unsigned)f.pn),
-                     dim3(kDetBlock), lds, st, f.pre, f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0,
-                     f.tw_stride, f.pcs, f.zero);
+  const dim3 g((unsigned)(rtiles * jtiles), (unsigned)f.pn);
+  if (fused_paired(f.m0)) {
+    if constexpr (GL == 1)
+      hipLaunchKernelGGL((det_fused_pair3_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre,
+                         f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs,
+                         f.zero, f.fixup);
+    else
+      hipLaunchKernelGGL((det_fused_pair_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre,
+                         f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs,
+                         f.zero, f.fixup);
+  } else
+    hipLaunchKernelGGL((det_fused_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre, f.detv,
+                       f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs, f.zero,
+                       f.fixup);
   return hipGetLastError();
 }
 

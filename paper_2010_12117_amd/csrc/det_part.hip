@@ -13,12 +13,19 @@ namespace pd {
                                         int, const PrimeConst*, hipStream_t);         \
   template hipError_t det_fused_launch<N, GL>(const FusedDetArgs&, hipStream_t);          \
   template hipError_t det_fused_batch_launch<N, GL>(const BDet*, int, int64_t, size_t,    \
-                                                    uint8_t*, hipStream_t);
+                                                    uint8_t*, bool, bool, hipStream_t);
+#define PD_LL(N)                                                                       \
+  template hipError_t det_ll_launch<N>(const FusedDetArgs&, hipStream_t);              \
+  template hipError_t det_ll_batch_launch<N>(const BDet*, int, int64_t, size_t, uint8_t*, \
+                                             hipStream_t);
 
 #if DET_PART == 0
 PD_DET(1, 1) PD_DET(2, 1) PD_DET(3, 1) PD_DET(4, 1) PD_DET(5, 1) PD_DET(6, 1)
 PD_DET(7, 1) PD_DET(8, 1) PD_DET(9, 1) PD_DET(10, 1) PD_DET(11, 1) PD_DET(12, 1)
+PD_LL(1) PD_LL(2) PD_LL(3) PD_LL(4) PD_LL(5) PD_LL(6)
+PD_LL(7) PD_LL(8) PD_LL(9) PD_LL(10) PD_LL(11) PD_LL(12)
 #elif DET_PART == 1
+PD_LL(13) PD_LL(14) PD_LL(15) PD_LL(16)
 PD_DET(2, 2) PD_DET(3, 2) PD_DET(4, 2) PD_DET(5, 2) PD_DET(6, 2) PD_DET(7, 2)
 PD_DET(8, 2) PD_DET(9, 2) PD_DET(10, 2) PD_DET(11, 2) PD_DET(12, 2) PD_DET(13, 2)
 PD_DET(14, 2) PD_DET(15, 2) PD_DET(16, 2)

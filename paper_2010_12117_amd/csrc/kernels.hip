@@ -453,7 +453,7 @@ hipError_t launch_expand(const MatPlan& P, const uint32_t* in, uint32_t* out, in
 
 template <int N, int GL>
 hipError_t launch_det_ng(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hipStream_t st) {
-  uint32_t* denv = (uint32_t*)(ws + P.off_den);
+  uint32_t* denv = (uint32_t*)(const_cast<uint8_t*>(ws) + P.off_den);
   if (!P.fused) {
     return det_launch<N, GL>((const uint32_t*)(ws + P.off_eval), detv, denv, P.G, P.pn, P.d_pc, st);
   }
@@ -471,6 +471,15 @@ hipError_t launch_det_ng(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hi
   f.pcs = P.d_pc;
   f.zero = P.d_zero;
   f.pn = P.pn;
+  f.fixup = false;
+  if constexpr (N <= kLLMaxN) {
+    if (P.det_ll) {
+      // left-looking pass, then the exchanging kernel repairs the points it could not do
+      const hipError_t e = det_ll_launch<N>(f, st);
+      if (e != hipSuccess) return e;
+      f.fixup = true;
+    }
+  }
   return det_fused_launch<N, GL>(f, st);
 }
 
@@ -483,9 +492,13 @@ struct SingleDet {
 
 template <int N, int GL>
 struct BatchDet {
-  static hipError_t run(const BDet* desc, int ndesc, int64_t vblocks, size_t lds, uint8_t* ws,
-                        hipStream_t st) {
-    return det_fused_batch_launch<N, GL>(desc, ndesc, vblocks, lds, ws, st);
+  static hipError_t run(int ll, bool pair, const BDet* desc, int ndesc, int64_t vblocks,
+                        size_t lds, uint8_t* ws, hipStream_t st) {
+    if (ll == 1) {
+      if constexpr (N <= kLLMaxN) return det_ll_batch_launch<N>(desc, ndesc, vblocks, lds, ws, st);
+      return hipErrorInvalidValue;
+    }
+    return det_fused_batch_launch<N, GL>(desc, ndesc, vblocks, lds, ws, pair, ll == 2, st);
   }
 };
 
@@ -684,9 +697,9 @@ hipError_t batch_garner(const BGarner* desc, int ndesc, int64_t vblocks, int pnm
   return launch_garner_batch<32>(desc, ndesc, vblocks, ws, out, out_offsets, st);
 }
 
-hipError_t batch_det(int n, int lanes, const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
-                     uint8_t* ws, hipStream_t st) {
-  return det_dispatch<BatchDet>(n, lanes, desc, ndesc, vblocks, lds, ws, st);
+hipError_t batch_det(int n, int lanes, int ll, bool pair, const BDet* desc, int ndesc,
+                     int64_t vblocks, size_t lds, uint8_t* ws, hipStream_t st) {
+  return det_dispatch<BatchDet>(n, lanes, ll, pair, desc, ndesc, vblocks, lds, ws, st);
 }
 
 }  // namespace pd

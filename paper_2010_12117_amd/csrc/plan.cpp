@@ -317,7 +317,8 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   if (P.fused) {
     constexpr size_t kFuseLds = 64 * 1024;
     const int64_t R = P.G / P.N[0];
-    const int per_block = 256 / P.det_lanes;
+    const int per_block = fused_slots(256, P.det_lanes, P.m[0]);
+    const int NJ = fused_jrange(P.N[0], P.m[0]);
     int Q = 16;
     while (Q > 1 && (Q > per_block || Q > R ||
                      (size_t)(P.nent | 1) * P.m[0] * Q * 4 > kFuseLds)) Q >>= 1;
@@ -327,12 +328,15 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
       const int J = per_block / Q;
       const int64_t base_blocks = (int64_t)P.pn * ((R + Q - 1) / Q);
       // enough blocks to fill 256 CUs several times; each block reuses its tile S / J times
-      int iters = (int)std::max<int64_t>(1, (int64_t)P.N[0] * base_blocks / (2048LL * J));
-      iters = std::min(iters, std::max(1, (P.N[0] + J - 1) / J));
+      int iters = (int)std::max<int64_t>(1, (int64_t)NJ * base_blocks / (2048LL * J));
+      iters = std::min(iters, std::max(1, (NJ + J - 1) / J));
       P.fuse_Q = Q;
       P.fuse_S = J * iters;
     }
   }
+  // Left-looking elimination (one lane per matrix, pivot rows only in registers) on request
+  // (flag bit 2) up to kLLMaxN; the exchanging kernel alone by default (bit 3).
+  if (P.fused && (flags & 4u) && !(flags & 8u)) P.det_ll = s.n <= kLLMaxN;
   if (P.fused) {
     // the pre-tensor is the output of the evaluation pass over variable 1 (pass index
     // k - 2 counting from the last variable; passes alternate tmpA, tmpB), or the residues

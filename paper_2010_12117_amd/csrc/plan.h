@@ -18,6 +18,21 @@ constexpr int kMaxN = 32;          // largest matrix order with a compiled elimi
 constexpr int kMaxEntryDeg = 31;   // per-variable entry degree (evaluation kernel registers)
 constexpr int kMaxGrid = 4096;     // per-variable grid (interpolation tile in LDS)
 constexpr int kMaxPrimes = 32;     // reconstruction kernel registers
+constexpr int kLLMaxN = 16;        // largest order with a left-looking elimination kernel
+constexpr int kLLMaxM = 8;         // its limit on coefficients in the first variable
+
+// Fused first-variable evaluation in pairs, for 2 <= m0 <= 4 coefficients in the first
+// variable (its grid N0 is then even): lanes l and l + 32 of a wave take the points j0 and
+// j0 + N0/2. Since w^{N0/2} = -1, f(w^{j0 + N0/2}) = E - O where f(w^{j0}) = E + O splits f
+// into its even and odd terms; the lower lane sums the even terms, the upper lane the odd
+// ones, and they exchange the sums. A block then covers the first variable's grid index j0
+// in [0, N0/2) only, with half as many matrices per j-row.
+PD_HD bool fused_paired(int m0) { return m0 >= 2 && m0 <= 4; }
+PD_HD int fused_jrange(int N0, int m0) { return fused_paired(m0) ? N0 / 2 : N0; }
+// matrices (lane groups) in one j-row of a block of `block` lanes
+PD_HD int fused_slots(int block, int lanes, int m0) {
+  return (fused_paired(m0) ? block / 2 : block) / lanes;
+}
 
 // The descending table of primes p in (2^30, 2^31) with p = 1 mod 2^16.
 const std::vector<uint32_t>& prime_table();
@@ -54,6 +69,7 @@ struct MatPlan {
 
   // fused first-variable evaluation + elimination (det_fused_kernel)
   bool fused = false;
+  bool det_ll = false;  // left-looking elimination pass before the exchanging kernel
   int fuse_Q = 1, fuse_S = 1;
   size_t off_pre = 0;  // [pn][n*n][m0][R] input of the fused kernel
 

@@ -259,6 +259,7 @@ polydet_status polydet_plan_query(polydet_plan_t plan, int32_t index, polydet_pl
   out->det_lanes = P.det_lanes;
   out->det_sign = P.det_sign;
   for (int i = 0; i < P.n && i < 32; ++i) out->row_order[i] = (uint8_t)P.row_order[i];
+  out->det_left_looking = P.det_ll ? 1 : 0;
   out->in_bytes = P.in_bytes;
   out->out_bytes = P.out_bytes;
   out->workspace_bytes = plan->plan.batch ? plan->plan.ws_bytes : P.ws_bytes;
@@ -324,7 +325,8 @@ static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
         e = pd::batch_expand((const pd::BExpand*)desc, L.ndesc, L.vblocks, ws, st);
         break;
       case pd::BLaunch::kDet:
-        e = pd::batch_det(L.n, L.lanes, (const pd::BDet*)desc, L.ndesc, L.vblocks, L.lds, ws, st);
+        e = pd::batch_det(L.n, L.lanes, L.ll, L.pair != 0, (const pd::BDet*)desc, L.ndesc,
+                          L.vblocks, L.lds, ws, st);
         break;
       case pd::BLaunch::kFinal:
         e = pd::batch_final((const pd::BFinal*)desc, L.ndesc, L.vblocks, ws, st);

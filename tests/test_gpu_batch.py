@@ -88,6 +88,13 @@ def mixed_batch(seed=0, count=40):
     mats.append(W.random_matrix(rng, 3, (9, 1), -5, 5))  # 10 coefficients in a later variable
     mats.append(W.random_matrix(rng, 3, (1, 9), -5, 5))
     mats.append(np.zeros((4, 4, 2, 2), dtype=np.int64))  # zero matrix
+    # first pivot (x1 - 1 or x1 + 1) vanishes at grid points whatever the row order
+    for n in (2, 6, 12):
+        v = W.random_matrix(rng, n, (1, 1), -9, 9)
+        v[:, 0] = 0
+        v[0, 0, 0, 0], v[0, 0, 1, 0] = -1, 1
+        v[1, 0, 0, 0], v[1, 0, 1, 0] = 1, 1
+        mats.append(v)
     return mats
 
 
@@ -100,6 +107,14 @@ def test_batch_matches_plain_single_and_oracle():
         n, deg = B.shape_of(a)
         expect = OD.det_pointwise(a, PL.det_degree_bound_from_shape(n, deg))
         assert box_to_dict(got[i]) == box_to_dict(expect), i
+
+
+def test_batch_left_looking_and_exchanging_agree():
+    mats = mixed_batch(seed=3)
+    ll, _ = solve_batch(mats, flags=pdm.DET_LEFT_LOOKING)
+    ex, _ = solve_batch(mats, flags=pdm.DET_EXCHANGE)
+    for i in range(len(mats)):
+        assert box_to_dict(ll[i]) == box_to_dict(ex[i]), i
 
 
 def test_batch_across_chunks(monkeypatch):

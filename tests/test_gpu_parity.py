@@ -102,9 +102,61 @@ def test_every_lane_mapping(n, lanes):
     rng = np.random.default_rng(2000 + 40 * n + lanes)
     arr = W.random_matrix(rng, n, (1,), -9, 9, zero_prob=0.35)
     log2 = {1: 0, 2: 1, 4: 2, 8: 3, 16: 4}[lanes]
-    got, pl, _ = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2))
+    got, pl, _ = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2) | pdm.DET_EXCHANGE)
     assert pl.info["det_lanes"] == lanes
     assert box_to_dict(got) == box_to_dict(oracle_box(arr))
+
+
+def vanishing_pivots(rng, n, deg, kind):
+    """Random matrix whose elimination meets a zero pivot at some grid points whatever row
+    order is taken. kind 0: column 0 is (x1 - 1, x1 + 1, 0, ..., 0), so the first pivot
+    vanishes at x1 = 1 or at x1 = -1 (both on every grid). kind 1: the leading 2 x 2 block
+    is [[1, x1], [1, 1]] with zeros below it in columns 0 and 1, so the second pivot is
+    1 - x1 or x1 - 1."""
+    a = W.random_matrix(rng, n, deg, -20, 20, zero_prob=0.2)
+    one = np.zeros(a.shape[2:], dtype=np.int64)
+    one[(0,) * len(deg)] = 1
+    x1 = np.zeros_like(one)
+    x1[(1,) + (0,) * (len(deg) - 1)] = 1
+    a[:, 0] = 0
+    if kind == 0:
+        a[0, 0] = x1 - one
+        if n > 1:
+            a[1, 0] = x1 + one
+    else:
+        a[:, 1] = 0
+        a[0, 0], a[0, 1], a[1, 0], a[1, 1] = one, x1, one, one
+    return a
+
+
+LL_CASES = [(n, kind) for n in (2, 3, 5, 8, 11, 12, 13, 16) for kind in (0, 1)]
+
+
+@pytest.mark.parametrize("n,kind", LL_CASES)
+def test_left_looking_repairs_zero_pivots(n, kind):
+    # the left-looking pass cannot exchange rows: points where a pivot vanishes mod p are
+    # recomputed by the exchanging kernel, and the result equals the exchanging kernel's
+    # at every grid point
+    rng = np.random.default_rng(700 + 2 * n + kind)
+    arr = vanishing_pivots(rng, n, (2, 1), kind)
+    a, pla, wsa = gpu_solve(arr, flags=pdm.DET_LEFT_LOOKING)
+    b, plb, wsb = gpu_solve(arr, flags=pdm.DET_EXCHANGE)
+    assert pla.info["det_left_looking"] == 1 and plb.info["det_left_looking"] == 0
+    assert box_to_dict(a) == box_to_dict(b) == box_to_dict(oracle_box(arr))
+    ia, ib = pla.info, plb.info
+    nb = 4 * ia["pn"] * ia["G"]
+    da = wsa.cpu().numpy()[ia["off_detv"]:ia["off_detv"] + nb]
+    db = wsb.cpu().numpy()[ib["off_detv"]:ib["off_detv"] + nb]
+    assert np.array_equal(da, db)
+
+
+@pytest.mark.parametrize("n", list(range(1, 17)))
+def test_left_looking_every_order(n):
+    rng = np.random.default_rng(800 + n)
+    arr = W.random_matrix(rng, n, (3, 1), -30, 30, zero_prob=0.3)
+    a, _, _ = gpu_solve(arr, flags=pdm.DET_LEFT_LOOKING)
+    b, _, _ = gpu_solve(arr, flags=pdm.DET_EXCHANGE)
+    assert box_to_dict(a) == box_to_dict(b) == box_to_dict(oracle_box(arr))
 
 
 def test_integer_matrices_extreme_values():

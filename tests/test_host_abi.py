@@ -183,3 +183,19 @@ def test_structural_row_order():
     # without coefficients the order is the identity
     info = pdm.plan(5, (1,), coeff_bits=3, flags=pdm.HOST_ONLY).info
     assert info["row_order"] == tuple(range(5)) and info["det_sign"] == 1
+
+
+def test_elimination_form_choice():
+    # the exchanging kernel alone by default; a left-looking pass on request for orders up
+    # to 16 when the first variable is evaluated inside the elimination kernel
+    H = pdm.HOST_ONLY
+    LL = pdm.DET_LEFT_LOOKING
+    for n in (1, 5, 12, 13, 16):
+        assert pdm.plan(n, (3, 3), coeff_bits=8, flags=H).info["det_left_looking"] == 0
+        assert pdm.plan(n, (3, 3), coeff_bits=8, flags=H | LL).info["det_left_looking"] == 1
+        assert pdm.plan(n, (3, 3), coeff_bits=8,
+                        flags=H | LL | pdm.DET_EXCHANGE).info["det_left_looking"] == 0
+        assert pdm.plan(n, (3, 3), coeff_bits=8,
+                        flags=H | LL | pdm.UNFUSED_EVAL).info["det_left_looking"] == 0
+    assert pdm.plan(17, (1,), coeff_bits=8, flags=H | LL).info["det_left_looking"] == 0
+    assert pdm.plan(4, (), coeff_bits=8, flags=H | LL).info["det_left_looking"] == 0
