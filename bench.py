@@ -15,6 +15,7 @@ import multiprocessing as mp
 import os
 import sys
 import time
+from concurrent.futures import TimeoutError as FutureTimeout
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -158,19 +159,36 @@ def bench_serving(args):
     large = sum(1 for a in jobs if a.shape[0] == 32 and a.ndim == 5 and a.shape[2] == 6)
     budget = int(args.serve_budget_gb * (1 << 30))
 
-    def run(rate):
+    def run(rate, label):
         srv = S.Server(memory_budget=budget, slots=args.slots)
         arr = S.poisson_arrivals(np.random.default_rng(77), len(jobs), rate) if rate else None
         t0 = time.perf_counter()
+        last = t0
         futs = []
+
+        def progress():
+            nonlocal last
+            now = time.perf_counter()
+            if now - last > 15:
+                done = sum(f.done() for f in futs)
+                print(f"serving: {label}: {len(futs)} submitted, {done} done, "
+                      f"{now - t0:.0f} s", file=sys.stderr, flush=True)
+                last = now
+
         for i, a in enumerate(jobs):
             if arr is not None:
                 wait = arr[i] - (time.perf_counter() - t0)
                 if wait > 0:
                     time.sleep(wait)
             futs.append(srv.submit(a))
+            progress()
         for f in futs:
-            f.result()
+            while True:
+                try:
+                    f.result(timeout=5)
+                    break
+                except FutureTimeout:
+                    progress()
         makespan = time.perf_counter() - t0
         srv.close()
         st = srv.stats()
@@ -178,15 +196,15 @@ def bench_serving(args):
         st["jobs_per_s"] = len(jobs) / makespan
         return st
 
-    run(0)  # warm-up: plans, kernels, allocator
+    run(0, "warm-up")  # plans, kernels, allocator
     torch.cuda.synchronize()
     print("serving: warm-up done", file=sys.stderr, flush=True)
-    cap = run(0)
+    cap = run(0, "capacity")
     capacity = cap["jobs_per_s"]
     print(f"serving: capacity {capacity:.1f} jobs/s", file=sys.stderr, flush=True)
     out = {"capacity": cap}
     for rho in (0.5, 0.8):
-        out[f"rho_{rho}"] = run(rho * capacity)
+        out[f"rho_{rho}"] = run(rho * capacity, f"rho {rho}")
         print(f"serving: rho {rho} done", file=sys.stderr, flush=True)
     line = {
         "metric": "serving: p50/p99 latency and throughput of exact determinant jobs, 1 GPU",

@@ -83,8 +83,8 @@ struct BLaunch {
   size_t lds;          // dynamic LDS per block
 };
 
-// Launchers (batch_kernels.hip and det_part.hip). `desc` points to device descriptors;
-// `grid` is the number of resident blocks that walk the virtual blocks.
+// Launchers (kernels.hip and det_part.hip). `desc` points to device descriptors;
+// the launches walk `vblocks` virtual blocks.
 hipError_t batch_reduce(const BReduce* desc, int ndesc, int64_t vblocks, const int64_t* coeffs,
                         const int64_t* coeff_offsets, uint8_t* ws, hipStream_t st);
 hipError_t batch_expand(const BExpand* desc, int ndesc, int64_t vblocks, uint8_t* ws,
@@ -107,8 +107,10 @@ template <int N>
 hipError_t det_ll_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
                                uint8_t* ws, hipStream_t st);
 
-// Virtual blocks are walked by at most this many resident blocks per launch.
+// Virtual blocks are walked by at most this many resident blocks per launch (all but the
+// elimination launches, which take one block per virtual block, at most kMaxGridBlocks).
 constexpr int64_t kPersistentBlocks = 256 * 8;
+constexpr int64_t kMaxGridBlocks = 0x7FFFFFFF;
 // Coefficients per variable handled by the batched evaluation (registers).
 constexpr int kBatchMaxM = 8;
 

@@ -214,7 +214,7 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         e.zero = P.d_zero;
         d.push_back(e);
         vb += (int64_t)P.pn * e.rtiles * e.jtiles;
-        lds = std::max(lds, (size_t)(P.nent | 1) * P.m[0] * P.fuse_Q * 4);
+        lds = std::max(lds, fused_tile_words(P.n, P.det_lanes, P.m[0], P.fuse_Q) * 4);
       }
       BLaunch L{};
       L.kind = BLaunch::kDet;

@@ -104,6 +104,20 @@ __device__ __forceinline__ DetFrac eliminate(uint32_t (&a)[(N + GL - 1) / GL][N]
   return f;
 }
 
+// Waves per SIMD asked of the compiler for the single-matrix paired kernel with one lane per
+// matrix. Left to itself the compiler lands a register or two above an occupancy step there
+// (169 at n = 12: two waves); the request is the lane's n^2 values plus kDetRegMargin, out
+// of 512 registers per lane, which gives 168 at n = 12 without spills. The other elimination
+// kernels need more than that margin (the request would spill) and get no request.
+constexpr int kDetRegMargin = 24;
+template <int N, int GL>
+constexpr int det_waves() {
+  if (GL != 1) return 1;  // 1: no constraint beyond the launch bounds
+  constexpr int regs = ((N * N + kDetRegMargin + 7) / 8) * 8;
+  constexpr int w = 512 / regs;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 // Unfused form: the matrix at each point is read from the full evaluation tensor
 // eval[pn][n*n][npts].
 template <int N, int GL>
@@ -140,24 +154,28 @@ __global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restri
 }
 
 // Stages columns r0 .. r0+Q-1 of the pre-tensor pre[n*n][m0][R] (one prime) in LDS as
-// tile[m][q][e] with row stride NEP = n*n | 1 (odd, so lanes reading different q hit
-// different banks, and the entry index e is an immediate offset). Zero entries and columns
-// past R are stored as zeros without reading memory.
-template <int N>
+// tile[m][q][i * NCP + col] with NCP >= n columns per row (the columns past n-1 hold zeros,
+// so that every lane of a lane group reads the same offsets) and row stride
+// NEP = n*NCP | 1 (odd, so lanes reading different q hit different banks, and the entry
+// offset is an immediate). Zero entries and points past R are stored as zeros without
+// reading memory.
+template <int N, int NCP>
 __device__ __forceinline__ void fill_tile(uint32_t* tile, const uint32_t* __restrict__ src,
                                           int64_t R, int m0, int Q, int64_t r0,
                                           const uint8_t* __restrict__ zero) {
-  constexpr int NE = N * N;
-  constexpr int NEP = NE | 1;
+  constexpr int NEC = N * NCP;
+  constexpr int NEP = NEC | 1;
   const int mq = m0 * Q;
-  for (int idx = threadIdx.x; idx < NE * mq; idx += kDetBlock) {
-    const int e = idx / mq;
-    const int rem = idx - e * mq;  // = m Q + q
+  for (int idx = threadIdx.x; idx < NEC * mq; idx += kDetBlock) {
+    const int ec = idx / mq;
+    const int rem = idx - ec * mq;  // = m Q + q
     const int q = rem % Q;
     const int m = rem / Q;
+    const int i = ec / NCP, col = ec - i * NCP;
+    const int e = i * N + col;
     uint32_t v = 0u;
-    if (!(zero && zero[e]) && r0 + q < R) v = src[((int64_t)e * m0 + m) * R + r0 + q];
-    tile[rem * NEP + e] = v;
+    if (col < N && !(zero && zero[e]) && r0 + q < R) v = src[((int64_t)e * m0 + m) * R + r0 + q];
+    tile[rem * NEP + ec] = v;
   }
 }
 
@@ -203,7 +221,8 @@ __device__ __forceinline__ void det_fused_body(
     bool fixup) {
   constexpr int C = (N + GL - 1) / GL;
   constexpr int NE = N * N;
-  constexpr int NEP = NE | 1;
+  constexpr int NCP = C * GL;  // tile columns per row, padded for the last lane slot
+  constexpr int NEP = (N * NCP) | 1;
   const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
   const int64_t rtiles = (R + Q - 1) / Q;
   const int64_t r0 = (bx % rtiles) * Q;
@@ -211,7 +230,7 @@ __device__ __forceinline__ void det_fused_body(
   const uint32_t* src = pre + (int64_t)prime * NE * m0 * R;
   const int NJ = PAIR ? N0 / 2 : N0;
   if (fixup && !block_needs_fixup(denv, R, N0, NJ, Q, S, r0, jbase, prime)) return;
-  fill_tile<N>(tile, src, R, m0, Q, r0, zero);
+  fill_tile<N, NCP>(tile, src, R, m0, Q, r0, zero);
   __syncthreads();
 
   // lane -> (half, pair index): lanes l and l + 32 of a wave share (slot, r, j0) when paired
@@ -226,10 +245,8 @@ __device__ __forceinline__ void det_fused_body(
   const int jj = slot / Q;
   const bool qvalid = r0 + q < R;
   const uint32_t* w0 = tw0 + (int64_t)prime * tw_stride;
-  // column offset of the lane within its slot, clamped for the padded columns of the last
-  // slot (their registers are zeroed after the evaluation)
-  const int tl = t < N - (C - 1) * GL ? t : N - 1 - (C - 1) * GL;
-  const int dl = tl - t;
+  // lanes of the last slot past column n - 1 read the tile's zero columns: their registers
+  // evaluate to 0, which the elimination expects
 
   for (int j = jbase; j < jbase + S && j < NJ; j += J) {
     const int j0 = j + jj;
@@ -248,7 +265,7 @@ __device__ __forceinline__ void det_fused_body(
       for (int c = 0; c < C; ++c) {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-          const int off = i * N + c * GL + (c == C - 1 ? dl : 0);
+          const int off = i * NCP + c * GL;
           const uint32_t v = mm2(ra[off], wa, rb[off], wb, p, pinv);
           // afterwards every lane holds E (the lower lane's v) and O (the upper lane's v)
           const auto eo = __builtin_amdgcn_permlane32_swap(v, v, false, false);
@@ -270,7 +287,7 @@ __device__ __forceinline__ void det_fused_body(
         for (int c = 0; c < C; ++c) {
 #pragma unroll
           for (int i = 0; i < N; ++i) {
-            const int off = i * N + c * GL + (c == C - 1 ? dl : 0);
+            const int off = i * NCP + c * GL;
             a[c][i] = mm2(r0w[off], one, r1w[off], w1, p, pinv);
             if ((c * N + i) % kEvalChunk == kEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
           }
@@ -281,7 +298,7 @@ __device__ __forceinline__ void det_fused_body(
 #pragma unroll
         for (int c = 0; c < C; ++c) {
 #pragma unroll
-          for (int i = 0; i < N; ++i) a[c][i] = r0w[i * N + c * GL + (c == C - 1 ? dl : 0)];
+          for (int i = 0; i < N; ++i) a[c][i] = r0w[i * NCP + c * GL];
         }
         mstart = 1;
       }
@@ -294,19 +311,13 @@ __device__ __forceinline__ void det_fused_body(
         for (int c = 0; c < C; ++c) {
 #pragma unroll
           for (int i = 0; i < N; ++i) {
-            const int off = i * N + c * GL + (c == C - 1 ? dl : 0);
+            const int off = i * NCP + c * GL;
             a[c][i] = addm(a[c][i], mm2(ra[off], wa, rb[off], wb, p, pinv), p);
             // bound the scheduler's window so that the LDS reads (one register each) are
             // not all hoisted ahead of the arithmetic
             if ((c * N + i) % kEvalChunk == kEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
           }
         }
-      }
-    }
-    if constexpr (C * GL > N) {
-      if ((C - 1) * GL + t >= N) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) a[C - 1][i] = 0u;
       }
     }
     const DetFrac d = eliminate<N, GL>(a, p, pinv, one);
@@ -329,20 +340,8 @@ __global__ __launch_bounds__(kDetBlock) void det_fused_kernel(
 }
 
 template <int N, int GL>
-__global__ __launch_bounds__(kDetBlock) void det_fused_pair_kernel(
-    const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
-    int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, bool fixup) {
-  extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
-  det_fused_body<N, GL, true>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs,
-                              zero, blockIdx.y, blockIdx.x, fixup);
-}
-
-// The same, held to three waves per SIMD. With one lane per matrix the compiler lands just
-// above 168 registers at n = 12 (two waves); at 168 it needs no spills. Used for lanes = 1.
-template <int N, int GL>
-__global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(3)))
-void det_fused_pair3_kernel(
+__global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_waves<N, GL>())))
+void det_fused_pair_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
     int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
     const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, bool fixup) {
@@ -357,17 +356,18 @@ template <int N, int GL, bool PAIR>
 __device__ __forceinline__ void det_fused_batch_body(uint32_t* tile, const BDet* __restrict__ desc,
                                                      int ndesc, int64_t vblocks,
                                                      uint8_t* __restrict__ ws, bool fixup) {
-  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
-    const BDet& d = desc[find_desc(desc, ndesc, vb)];
-    const int64_t local = vb - d.block0;
-    const int64_t per_prime = d.rtiles * d.jtiles;
-    const int prime = (int)(local / per_prime);
-    det_fused_body<N, GL, PAIR>(tile, (const uint32_t*)(ws + d.pre_off),
-                                (uint32_t*)(ws + d.detv_off), (uint32_t*)(ws + d.den_off), d.R,
-                                d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride, d.pc, d.zero, prime,
-                                local - (int64_t)prime * per_prime, fixup);
-    __syncthreads();  // the next virtual block refills the tile
-  }
+  // One block per virtual block (no persistent loop: the loop's state costs registers that
+  // the elimination needs).
+  const int64_t vb = blockIdx.x;
+  if (vb >= vblocks) return;
+  const BDet& d = desc[find_desc(desc, ndesc, vb)];
+  const int64_t local = vb - d.block0;
+  const int64_t per_prime = d.rtiles * d.jtiles;
+  const int prime = (int)(local / per_prime);
+  det_fused_body<N, GL, PAIR>(tile, (const uint32_t*)(ws + d.pre_off),
+                              (uint32_t*)(ws + d.detv_off), (uint32_t*)(ws + d.den_off), d.R,
+                              d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride, d.pc, d.zero, prime,
+                              local - (int64_t)prime * per_prime, fixup);
 }
 
 template <int N, int GL>
@@ -379,8 +379,9 @@ __global__ __launch_bounds__(kDetBlock) void det_fused_batch_kernel(
 }
 
 template <int N, int GL>
-__global__ __launch_bounds__(kDetBlock) void det_fused_pair_batch_kernel(const BDet* __restrict__ desc, int ndesc, int64_t vblocks,
-                                 uint8_t* __restrict__ ws, bool fixup) {
+__global__ __launch_bounds__(kDetBlock) void det_fused_pair_batch_kernel(
+    const BDet* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws,
+    bool fixup) {
   extern __shared__ uint32_t tile[];
   det_fused_batch_body<N, GL, true>(tile, desc, ndesc, vblocks, ws, fixup);
 }
@@ -490,7 +491,7 @@ __device__ __forceinline__ void det_ll_body(
   const int64_t rtiles = (R + Q - 1) / Q;
   const int64_t r0 = (bx % rtiles) * Q;
   const int jbase = (int)(bx / rtiles) * S;
-  fill_tile<N>(tile, pre + (int64_t)prime * NE * m0 * R, R, m0, Q, r0, zero);
+  fill_tile<N, N>(tile, pre + (int64_t)prime * NE * m0 * R, R, m0, Q, r0, zero);
   __syncthreads();
 
   const int q = (int)(threadIdx.x % Q);
@@ -545,16 +546,15 @@ template <int N>
 __global__ __launch_bounds__(kDetBlock) void det_ll_batch_kernel(
     const BDet* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws) {
   extern __shared__ uint32_t tile[];
-  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
-    const BDet& d = desc[find_desc(desc, ndesc, vb)];
-    const int64_t local = vb - d.block0;
-    const int64_t per_prime = d.rtiles * d.jtiles;
-    const int prime = (int)(local / per_prime);
-    det_ll_body<N>(tile, (const uint32_t*)(ws + d.pre_off), (uint32_t*)(ws + d.detv_off),
-                   (uint32_t*)(ws + d.den_off), d.R, d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride,
-                   d.pc, d.zero, prime, local - (int64_t)prime * per_prime);
-    __syncthreads();  // the next virtual block refills the tile
-  }
+  const int64_t vb = blockIdx.x;  // one block per virtual block, as in the exchanging kernel
+  if (vb >= vblocks) return;
+  const BDet& d = desc[find_desc(desc, ndesc, vb)];
+  const int64_t local = vb - d.block0;
+  const int64_t per_prime = d.rtiles * d.jtiles;
+  const int prime = (int)(local / per_prime);
+  det_ll_body<N>(tile, (const uint32_t*)(ws + d.pre_off), (uint32_t*)(ws + d.detv_off),
+                 (uint32_t*)(ws + d.den_off), d.R, d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride,
+                 d.pc, d.zero, prime, local - (int64_t)prime * per_prime);
 }
 
 template <int N, int GL>
@@ -570,8 +570,9 @@ hipError_t det_launch(const uint32_t* eval, uint32_t* detv, uint32_t* denv, int6
 template <int N, int GL>
 hipError_t det_fused_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
                                   uint8_t* ws, bool pair, bool fixup, hipStream_t st) {
-  const int64_t grid = vblocks < kPersistentBlocks ? vblocks : kPersistentBlocks;
-  const dim3 g((unsigned)(grid < 1 ? 1 : grid));
+  if (vblocks < 1) return hipSuccess;
+  if (vblocks > kMaxGridBlocks) return hipErrorInvalidConfiguration;
+  const dim3 g((unsigned)vblocks);
   if (pair)
     hipLaunchKernelGGL((det_fused_pair_batch_kernel<N, GL>), g, dim3(kDetBlock), lds, st, desc,
                        ndesc, vblocks, ws, fixup);
@@ -586,7 +587,7 @@ hipError_t det_ll_launch(const FusedDetArgs& f, hipStream_t st) {
   const int64_t rtiles = (f.R + f.Q - 1) / f.Q;
   const int Sl = fused_paired(f.m0) ? 2 * f.S : f.S;
   const int64_t jtiles = (f.N0 + Sl - 1) / Sl;
-  const size_t lds = (size_t)((N * N) | 1) * f.m0 * f.Q * sizeof(uint32_t);
+  const size_t lds = fused_tile_words(N, 1, f.m0, f.Q) * sizeof(uint32_t);
   hipLaunchKernelGGL((det_ll_kernel<N>), dim3((unsigned)(rtiles * jtiles), (unsigned)f.pn),
                      dim3(kDetBlock), lds, st, f.pre, f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S,
                      f.tw0, f.tw_stride, f.pcs, f.zero);
@@ -596,9 +597,10 @@ hipError_t det_ll_launch(const FusedDetArgs& f, hipStream_t st) {
 template <int N>
 hipError_t det_ll_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
                                uint8_t* ws, hipStream_t st) {
-  const int64_t grid = vblocks < kPersistentBlocks ? vblocks : kPersistentBlocks;
-  hipLaunchKernelGGL((det_ll_batch_kernel<N>), dim3((unsigned)(grid < 1 ? 1 : grid)),
-                     dim3(kDetBlock), lds, st, desc, ndesc, vblocks, ws);
+  if (vblocks < 1) return hipSuccess;
+  if (vblocks > kMaxGridBlocks) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((det_ll_batch_kernel<N>), dim3((unsigned)vblocks), dim3(kDetBlock), lds, st,
+                     desc, ndesc, vblocks, ws);
   return hipGetLastError();
 }
 
@@ -606,18 +608,13 @@ template <int N, int GL>
 hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st) {
   const int64_t rtiles = (f.R + f.Q - 1) / f.Q;
   const int64_t jtiles = (fused_jrange(f.N0, f.m0) + f.S - 1) / f.S;
-  const size_t lds = (size_t)((N * N) | 1) * f.m0 * f.Q * sizeof(uint32_t);
+  const size_t lds = fused_tile_words(N, GL, f.m0, f.Q) * sizeof(uint32_t);
   const dim3 g((unsigned)(rtiles * jtiles), (unsigned)f.pn);
-  if (fused_paired(f.m0)) {
-    if constexpr (GL == 1)
-      hipLaunchKernelGGL((det_fused_pair3_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre,
-                         f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs,
-                         f.zero, f.fixup);
-    else
-      hipLaunchKernelGGL((det_fused_pair_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre,
-                         f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs,
-                         f.zero, f.fixup);
-  } else
+  if (fused_paired(f.m0))
+    hipLaunchKernelGGL((det_fused_pair_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre,
+                       f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs,
+                       f.zero, f.fixup);
+  else
     hipLaunchKernelGGL((det_fused_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre, f.detv,
                        f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs, f.zero,
                        f.fixup);

@@ -321,8 +321,8 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     const int NJ = fused_jrange(P.N[0], P.m[0]);
     int Q = 16;
     while (Q > 1 && (Q > per_block || Q > R ||
-                     (size_t)(P.nent | 1) * P.m[0] * Q * 4 > kFuseLds)) Q >>= 1;
-    if ((size_t)(P.nent | 1) * P.m[0] * Q * 4 > kFuseLds) {
+                     fused_tile_words(P.n, P.det_lanes, P.m[0], Q) * 4 > kFuseLds)) Q >>= 1;
+    if (fused_tile_words(P.n, P.det_lanes, P.m[0], Q) * 4 > kFuseLds) {
       P.fused = false;  // the tile does not fit: evaluate in full, then eliminate
     } else {
       const int J = per_block / Q;

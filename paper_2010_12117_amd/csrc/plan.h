@@ -34,6 +34,13 @@ PD_HD int fused_slots(int block, int lanes, int m0) {
   return (fused_paired(m0) ? block / 2 : block) / lanes;
 }
 
+// LDS words of a fused elimination block's tile: m0 coefficient rows of Q points, each a
+// matrix whose n rows are padded to a multiple of the lanes per matrix, with an odd stride.
+PD_HD size_t fused_tile_words(int n, int lanes, int m0, int Q) {
+  const int ncp = (n + lanes - 1) / lanes * lanes;
+  return (size_t)((n * ncp) | 1) * m0 * Q;
+}
+
 // The descending table of primes p in (2^30, 2^31) with p = 1 mod 2^16.
 const std::vector<uint32_t>& prime_table();
 uint32_t primitive_root(uint32_t p);

@@ -51,7 +51,7 @@ class Result:
         return out.reshape(box) if box else out.reshape(())
 
 
-@dataclass
+@dataclass(eq=False)  # jobs are compared by identity (they hold arrays)
 class _Job:
     coeffs: np.ndarray
     plan: B.Plan
@@ -172,6 +172,19 @@ class Server:
         job.future.set_result(res)
 
     def _loop(self):
+        try:
+            self._serve()
+        except BaseException as e:  # pragma: no cover - fail every waiting client, loudly
+            with self.lock:
+                self.closed = True
+                pending = list(self.running) + list(self.queue)
+                self.running, self.queue = [], collections.deque()
+            for j in pending:
+                if not j.future.done():
+                    j.future.set_exception(e)
+            raise
+
+    def _serve(self):
         while True:
             with self.lock:
                 done = [j for j in self.running if j.done_event.query()]

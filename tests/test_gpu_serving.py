@@ -58,3 +58,20 @@ def test_oversized_job_is_rejected():
     with pytest.raises(ValueError):
         srv.submit(W.config2())
     srv.close()
+
+
+def test_out_of_order_completion():
+    # a large job first, then small ones on the other slots: the small ones finish first and
+    # leave the running list from the middle
+    rng = np.random.default_rng(77)
+    big = W.random_matrix(rng, 24, (3, 3, 3), -1000, 1000)  # about 0.1 s of GPU work
+    jobs = [big] + small_jobs(5, 16)
+    srv = S.Server(memory_budget=8 << 30, slots=4)
+    futs = [srv.submit(a) for a in jobs]
+    results = [f.result(timeout=120) for f in futs]
+    srv.close()
+    assert srv.stats()["completed"] == len(jobs)
+    order = sorted(range(len(jobs)), key=lambda i: results[i].finished)
+    assert order[0] != 0  # some small job finished before the first one
+    for a, r in zip(jobs, results):
+        assert np.array_equal(r.limbs, alone(a))

@@ -199,3 +199,14 @@ def test_elimination_form_choice():
                         flags=H | LL | pdm.UNFUSED_EVAL).info["det_left_looking"] == 0
     assert pdm.plan(17, (1,), coeff_bits=8, flags=H | LL).info["det_left_looking"] == 0
     assert pdm.plan(4, (), coeff_bits=8, flags=H | LL).info["det_left_looking"] == 0
+
+
+def test_serving_jobs_compare_by_identity():
+    # the server removes finished jobs from its running list; jobs hold arrays of any shape,
+    # so equality must be identity
+    from paper_2010_12117_amd import serving as S
+    jobs = [S._Job(np.zeros((n, n, 2)), None, 0, None, 0.0) for n in (3, 4, 4)]
+    running = list(jobs)
+    running.remove(jobs[2])
+    running.remove(jobs[0])
+    assert running == [jobs[1]]
