@@ -165,17 +165,22 @@ __device__ __forceinline__ void fill_tile(uint32_t* tile, const uint32_t* __rest
                                           const uint8_t* __restrict__ zero) {
   constexpr int NEC = N * NCP;
   constexpr int NEP = NEC | 1;
-  const int mq = m0 * Q;
-  for (int idx = threadIdx.x; idx < NEC * mq; idx += kDetBlock) {
-    const int ec = idx / mq;
-    const int rem = idx - ec * mq;  // = m Q + q
-    const int q = rem % Q;
-    const int m = rem / Q;
+  // Q is a power of two: q = idx mod Q by mask, the padded entry index ec = idx / Q by shift;
+  // every thread then copies its (ec, q) for each of the m0 coefficients
+  const int qs = __builtin_ctz((unsigned)Q);
+  for (int idx = threadIdx.x; idx < NEC * Q; idx += kDetBlock) {
+    const int q = idx & (Q - 1);
+    const int ec = idx >> qs;
     const int i = ec / NCP, col = ec - i * NCP;
     const int e = i * N + col;
-    uint32_t v = 0u;
-    if (col < N && !(zero && zero[e]) && r0 + q < R) v = src[((int64_t)e * m0 + m) * R + r0 + q];
-    tile[rem * NEP + ec] = v;
+    const bool live = col < N && !(zero && zero[e]) && r0 + q < R;
+    uint32_t* d = tile + q * NEP + ec;
+    if (live) {
+      const uint32_t* s = src + (int64_t)e * m0 * R + r0 + q;
+      for (int m = 0; m < m0; ++m) d[m * Q * NEP] = s[(int64_t)m * R];
+    } else {
+      for (int m = 0; m < m0; ++m) d[m * Q * NEP] = 0u;
+    }
   }
 }
 
@@ -231,6 +236,14 @@ __device__ __forceinline__ void det_fused_body(
   const int NJ = PAIR ? N0 / 2 : N0;
   if (fixup && !block_needs_fixup(denv, R, N0, NJ, Q, S, r0, jbase, prime)) return;
   fill_tile<N, NCP>(tile, src, R, m0, Q, r0, zero);
+  // Structurally zero entries as a wave-uniform bit mask (one lane per matrix only): the
+  // paired evaluation branches around them (scalar branches; their registers are set to 0).
+  uint64_t zm[(NE + 63) / 64];
+#pragma unroll
+  for (int w = 0; w < (NE + 63) / 64; ++w) {
+    const int e = w * 64 + (int)(threadIdx.x & 63);
+    zm[w] = (GL == 1 && zero) ? __ballot(e < NE && zero[e] != 0) : 0ull;
+  }
   __syncthreads();
 
   // lane -> (half, pair index): lanes l and l + 32 of a wave share (slot, r, j0) when paired
@@ -254,6 +267,10 @@ __device__ __forceinline__ void det_fused_body(
     const int j0c = j0 < NJ ? j0 : NJ - 1;
     uint32_t a[C][N];
     if constexpr (PAIR) {
+      // an opaque copy per point keeps the compiler from hoisting all n^2 branch conditions
+      // out of the loop (they would be spilled to VGPR lanes and read back one by one)
+#pragma unroll
+      for (int w = 0; w < (NE + 63) / 64; ++w) asm volatile("" : "+s"(zm[w]));
       // terms m = half and m = half + 2 of every entry, weight w0^{m j0} (0 past m0 - 1,
       // where the row index is clamped to a valid row); w0^0 is the representative of 1
       const int ma = half, mb = half + 2;
@@ -261,16 +278,20 @@ __device__ __forceinline__ void det_fused_body(
       const uint32_t wb = mb < m0 ? w0[(mb * j0c) & (N0 - 1)] : 0u;
       const uint32_t* ra = tile + ((ma < m0 ? ma : m0 - 1) * Q + q) * NEP + t;
       const uint32_t* rb = tile + ((mb < m0 ? mb : m0 - 1) * Q + q) * NEP + t;
+      const uint32_t sm = half ? ~0u : 0u, sc = half ? p + 1u : 0u;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
           const int off = i * NCP + c * GL;
-          const uint32_t v = mm2(ra[off], wa, rb[off], wb, p, pinv);
-          // afterwards every lane holds E (the lower lane's v) and O (the upper lane's v)
-          const auto eo = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-          a[c][i] = fold(eo[0] + (half ? p - eo[1] : eo[1]), p);
-          if ((c * N + i) % kEvalChunk == kEvalChunk - 1) __builtin_amdgcn_sched_barrier(0);
+          const int e = i * N + c;  // the entry's index when GL == 1
+          if (GL == 1 && ((zm[e >> 6] >> (e & 63)) & 1ull)) {
+            a[c][i] = 0u;
+          } else {
+            const uint32_t v = mm2(ra[off], wa, rb[off], wb, p, pinv);
+            const auto eo = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+            a[c][i] = fold(eo[0] + (eo[1] ^ sm) + sc, p);
+          }
         }
       }
     } else {
