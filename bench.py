@@ -33,7 +33,7 @@ ALU_PEAK_UPDATES = CU * CLOCK_HZ * UPDATES_PER_CLK_CU
 # HBM bytes per launch of the fused elimination kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB copy (profiles/config2_hbm_traffic.md),
 # valid only for the kernel sources they were taken with (hash of det_impl.h + modarith.h).
-DET_TRAFFIC = {"sources_sha256_16": "0c3cafd694df0f5e", "bytes": 94.9e6 + 14.7e6}
+DET_TRAFFIC = {"sources_sha256_16": "430dfe8e2a1c663c", "bytes": 94.5e6 + 14.7e6}
 
 
 def kernel_sources_hash() -> str:
@@ -223,11 +223,10 @@ def det_kernel_name(info):
     n, lanes = info["n"], info["det_lanes"]
     m0 = info["deg"][0] + 1 if info["nvars"] else 1
     paired = 2 <= m0 <= 4  # first-variable points j0, j0 + N0/2 built by two lanes
-    fused = (("det_fused_pair3_kernel" if lanes == 1 else "det_fused_pair_kernel")
-             if paired else "det_fused_kernel") + f"<{n},{lanes}>"
+    fused = ("det_fused_pair_kernel" if paired else "det_fused_kernel") + f"<{n},{lanes}>"
     if info["det_left_looking"]:
-        return f"det_ll_kernel<{n}> + repair {fused} + finalize_kernel"
-    return f"{fused} + finalize_kernel"
+        return f"det_ll_kernel<{n}> + repair {fused}"
+    return fused
 
 
 def main():

@@ -105,7 +105,9 @@ typedef struct polydet_shape {
  * each stage (read by polydet_stage_times). Solves of such a plan must not overlap. */
 #define POLYDET_STAGE_TIMING ((uint32_t)1u << 30)
 
-#define POLYDET_NUM_STAGES 5 /* reduce, evaluate, determinants, interpolate, reconstruct */
+/* reduce, evaluate, determinants (the elimination kernels: numerator and denominator per
+ * point), finalize (det = num / den), interpolate, reconstruct */
+#define POLYDET_NUM_STAGES 6
 
 /* What a plan needs and produces. Workspace offsets (bytes) locate the intermediate stages
  * for inspection after a solve on the same stream has completed:
@@ -188,9 +190,9 @@ polydet_status polydet_solve_batch(polydet_plan_t plan, const int64_t* d_coeffs,
 
 /* Device time per stage of the solves of a plan made with POLYDET_STAGE_TIMING (the
  * paper's tables report the same split: FFT, DET, IFFT, CRT). Waits for the recorded
- * solves, writes the summed milliseconds of each stage (reduce, evaluate, determinants,
- * interpolate, reconstruct) to ms[0..4] and the number of solves to *solves, and resets the
- * sums. EINVAL if the plan was made without the flag. */
+ * solves, writes the summed milliseconds of each stage (POLYDET_NUM_STAGES of them, in the
+ * order listed there) to ms[] and the number of solves to *solves, and resets the sums.
+ * EINVAL if the plan was made without the flag. */
 polydet_status polydet_stage_times(polydet_plan_t plan, double ms[POLYDET_NUM_STAGES],
                                    int64_t* solves);
 

@@ -38,7 +38,7 @@ DET_LEFT_LOOKING = 4
 DET_EXCHANGE = 8
 HOST_ONLY = 1 << 31
 STAGE_TIMING = 1 << 30
-STAGES = ("reduce", "evaluate", "determinants", "interpolate", "reconstruct")
+STAGES = ("reduce", "evaluate", "determinants", "finalize", "interpolate", "reconstruct")
 
 
 class PolydetError(RuntimeError):

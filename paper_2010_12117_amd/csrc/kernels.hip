@@ -615,9 +615,11 @@ int64_t finalize_threads(int64_t G, int pn) {
 }
 
 hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st) {
-  hipError_t e = det_dispatch<SingleDet>(P.n, P.det_lanes, P, (const uint8_t*)ws,
-                                         (uint32_t*)(ws + P.off_detv), st);
-  if (e != hipSuccess) return e;
+  return det_dispatch<SingleDet>(P.n, P.det_lanes, P, (const uint8_t*)ws,
+                                 (uint32_t*)(ws + P.off_detv), st);
+}
+
+hipError_t run_finalize(const MatPlan& P, uint8_t* ws, hipStream_t st) {
   hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(finalize_threads(P.G, P.pn))), dim3(kBlock),
                      0, st, (uint32_t*)(ws + P.off_detv), (const uint32_t*)(ws + P.off_den), P.G,
                      P.pn, P.d_pc);

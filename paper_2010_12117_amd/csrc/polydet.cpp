@@ -1,5 +1,5 @@
 // C-ABI of the library (include/polydet.h): plan construction, queries and the solve that
-// enqueues the five stages of Algorithm 1 (Wei & Chen, arXiv 2010.12117) on one stream.
+// enqueues the stages of Algorithm 1 (Wei & Chen, arXiv 2010.12117) on one stream.
 #include "polydet.h"
 
 #include <hip/hip_runtime_api.h>
@@ -204,10 +204,12 @@ polydet_status run_one(const pd::MatPlan& P, const int64_t* d_coeffs, uint32_t* 
   if ((e = mark(2)) != hipSuccess) return hip_fail(e, "stage timing");
   if ((e = pd::run_det(P, ws, st)) != hipSuccess) return hip_fail(e, "determinants");
   if ((e = mark(3)) != hipSuccess) return hip_fail(e, "stage timing");
-  if ((e = pd::run_interpolate(P, ws, st)) != hipSuccess) return hip_fail(e, "interpolate");
+  if ((e = pd::run_finalize(P, ws, st)) != hipSuccess) return hip_fail(e, "finalize");
   if ((e = mark(4)) != hipSuccess) return hip_fail(e, "stage timing");
-  if ((e = pd::run_reconstruct(P, ws, d_out, st)) != hipSuccess) return hip_fail(e, "reconstruct");
+  if ((e = pd::run_interpolate(P, ws, st)) != hipSuccess) return hip_fail(e, "interpolate");
   if ((e = mark(5)) != hipSuccess) return hip_fail(e, "stage timing");
+  if ((e = pd::run_reconstruct(P, ws, d_out, st)) != hipSuccess) return hip_fail(e, "reconstruct");
+  if ((e = mark(6)) != hipSuccess) return hip_fail(e, "stage timing");
   return POLYDET_OK;
 }
 
