@@ -204,6 +204,31 @@ const char* polydet_status_string(polydet_status status);
 const char* polydet_last_error(void);
 
 /* Limits of this build: maximum n, nvars, N[v] and pn. Any pointer may be NULL. */
+/* Launch-mapping table for the elimination kernel, per class c and matrix order n (1..32;
+ * index 0 is unused). Class 0: the first variable has 2 to 4 coefficients (its evaluation is
+ * paired across the wave's halves); class 1: any other matrix with at least one variable.
+ * An entry of 0 keeps the built-in choice; flags given to polydet_plan override the table.
+ *   lanes         lanes that share one matrix: 1, 2, 4, 8 or 16 (the pairs the build
+ *                 compiles: 1 for n <= 12, 2 for 2..16, 4 for 4..24, 8 for n >= 8, 16 for
+ *                 n >= 16)
+ *   left_looking  1: left-looking pass and repair (n <= 16); 2: the exchanging kernel alone
+ *   tile_points   upper limit on the points per LDS tile of a block (Q): 1, 2, 4, 8 or 16
+ * The table is process-wide and read when a plan is built; plans built earlier keep their
+ * mapping. It is chosen by measurement (the package's autotuner); no choice in it changes a
+ * result. */
+#define POLYDET_TUNE_ORDERS 33
+typedef struct polydet_tuning {
+  int32_t lanes[2][POLYDET_TUNE_ORDERS];
+  int32_t left_looking[2][POLYDET_TUNE_ORDERS];
+  int32_t tile_points[2][POLYDET_TUNE_ORDERS];
+} polydet_tuning;
+
+/* Install a table (copied), or the built-in choices with NULL. EINVAL, and no change, if an
+ * entry is outside the values above or names a lanes/order pair the build does not compile. */
+polydet_status polydet_set_tuning(const polydet_tuning* table);
+/* The table in use (all zeros when none is installed). EINVAL for NULL. */
+polydet_status polydet_get_tuning(polydet_tuning* out);
+
 void polydet_limits(int32_t* max_n, int32_t* max_vars, int32_t* max_grid_per_var,
                     int32_t* max_primes);
 

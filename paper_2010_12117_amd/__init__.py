@@ -2,16 +2,17 @@
 
 The modular method of Wei & Chen (arXiv 2010.12117, Algorithm 1) as hand-written HIP
 kernels for gfx950 behind a C ABI (include/polydet.h); this package is the thin Python
-binding (binding.py) and the build script (build.py).
+binding (binding.py), the build script (build.py), the launch-mapping autotuner
+(autotune.py) and a request loop for serving (serving.py).
 """
 from .binding import (DET_LANES_LOG2, FORCE_PN, HOST_ONLY, PRIME_OFFSET, STAGE_TIMING, STAGES,
                       UNFUSED_EVAL, BATCH_PLAIN, DET_LEFT_LOOKING, DET_EXCHANGE,
                       Plan, PolydetError,
-                      det, limbs_to_ints, limits, load_library, plan, plan_batch,
-                      solve_batch_device, solve_device)
+                      det, get_tuning, limbs_to_ints, limits, load_library, plan, plan_batch,
+                      set_tuning, solve_batch_device, solve_device)
 
 __all__ = ["DET_LANES_LOG2", "FORCE_PN", "HOST_ONLY", "PRIME_OFFSET", "STAGE_TIMING", "STAGES",
            "UNFUSED_EVAL", "BATCH_PLAIN", "DET_LEFT_LOOKING", "DET_EXCHANGE",
            "Plan", "PolydetError",
-           "det", "limbs_to_ints", "limits", "load_library", "plan", "plan_batch",
-           "solve_batch_device", "solve_device"]
+           "det", "get_tuning", "limbs_to_ints", "limits", "load_library", "plan", "plan_batch",
+           "set_tuning", "solve_batch_device", "solve_device"]

@@ -8,6 +8,7 @@ missing, loading fails with an error that says how to build it.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from typing import List, Optional, Sequence
 
@@ -65,10 +66,20 @@ class PlanInfo(ctypes.Structure):
                 ("row_order", ctypes.c_uint8 * 32), ("det_left_looking", ctypes.c_int32)]
 
 
+TUNE_ORDERS = 33
+
+
+class Tuning(ctypes.Structure):
+    """polydet_tuning: [class][n] launch-mapping entries, 0 = built-in choice."""
+    _fields_ = [("lanes", (ctypes.c_int32 * TUNE_ORDERS) * 2),
+                ("left_looking", (ctypes.c_int32 * TUNE_ORDERS) * 2),
+                ("tile_points", (ctypes.c_int32 * TUNE_ORDERS) * 2)]
+
+
 EXPORTS = ["polydet_plan", "polydet_plan_batch", "polydet_plan_query", "polydet_plan_primes",
            "polydet_solve", "polydet_solve_batch", "polydet_plan_destroy",
            "polydet_status_string", "polydet_last_error", "polydet_limits",
-           "polydet_stage_times"]
+           "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning"]
 
 _lib = None
 
@@ -81,6 +92,13 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2010_12117_amd.build`"
                           " (the determinant path has no fallback)")
+    # PyTorch, which owns device memory and streams here, ships its own HIP runtime under the
+    # same soname as the system's. Whichever loads first serves the whole process, so torch
+    # goes first: loaded the other way round, torch finds no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i32, u32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64, ctypes.c_size_t
     P64 = ctypes.POINTER(ctypes.c_int64)
@@ -100,12 +118,56 @@ def load_library(path: str = LIB_PATH):
     lib.polydet_limits.argtypes = [ctypes.POINTER(i32)] * 4
     lib.polydet_limits.restype = None
     lib.polydet_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), P64]
+    lib.polydet_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.polydet_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     for name in ["polydet_plan", "polydet_plan_batch", "polydet_plan_query",
                  "polydet_plan_primes", "polydet_solve", "polydet_solve_batch",
-                 "polydet_stage_times"]:
+                 "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
+    _install_default_tuning()
     return lib
+
+
+# The launch-mapping table measured on the MI355X by autotune.py, shipped with the package.
+# POLYDET_TUNING names another table file, or "builtin" for the library's own choices.
+DEFAULT_TUNING = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
+
+
+def _install_default_tuning():
+    path = os.environ.get("POLYDET_TUNING", DEFAULT_TUNING)
+    if path == "builtin" or not os.path.exists(path):
+        return
+    with open(path) as f:
+        set_tuning(json.load(f))
+
+
+def set_tuning(table: Optional[dict]):
+    """Install a launch-mapping table: {"lanes"|"left_looking"|"tile_points": {"paired"|
+    "other": {n: value}}}; None restores the library's built-in choices."""
+    lib = load_library()
+    if table is None:
+        _check(lib.polydet_set_tuning(None))
+        return
+    t = Tuning()
+    for field in ("lanes", "left_looking", "tile_points"):
+        for c, cls in enumerate(("paired", "other")):
+            for n, v in table.get(field, {}).get(cls, {}).items():
+                getattr(t, field)[c][int(n)] = int(v)
+    _check(lib.polydet_set_tuning(ctypes.byref(t)))
+
+
+def get_tuning() -> dict:
+    """The table in use, in set_tuning's form (zero entries left out)."""
+    lib = load_library()
+    t = Tuning()
+    _check(lib.polydet_get_tuning(ctypes.byref(t)))
+    out = {}
+    for field in ("lanes", "left_looking", "tile_points"):
+        out[field] = {cls: {n: int(getattr(t, field)[c][n]) for n in range(TUNE_ORDERS)
+                            if getattr(t, field)[c][n]}
+                      for c, cls in enumerate(("paired", "other"))}
+    return out
 
 
 def _check(status: int):

@@ -6,10 +6,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 namespace pd {
 
 namespace {
+
+std::mutex g_tuning_mu;
+Tuning g_tuning;
 
 uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) {
   return (uint64_t)((unsigned __int128)a * b % m);
@@ -282,7 +286,11 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     P.pc[i] = c;
   }
 
+  // the measured launch-mapping table, where it has an entry for this order and class
+  const Tuning tune = get_tuning();
+  const int tclass = (s.k >= 1 && fused_paired(P.m[0])) ? 0 : 1;
   P.det_lanes = default_det_lanes(P.n);
+  if (tune.lanes[tclass][P.n] > 0) P.det_lanes = tune.lanes[tclass][P.n];
   const int dl = (int)((flags >> 4) & 0xF);
   if (dl) {
     const int want = 1 << (dl - 1);
@@ -319,7 +327,7 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     const int64_t R = P.G / P.N[0];
     const int per_block = fused_slots(256, P.det_lanes, P.m[0]);
     const int NJ = fused_jrange(P.N[0], P.m[0]);
-    int Q = 16;
+    int Q = tune.tile_points[tclass][P.n] > 0 ? tune.tile_points[tclass][P.n] : 16;
     while (Q > 1 && (Q > per_block || Q > R ||
                      fused_tile_words(P.n, P.det_lanes, P.m[0], Q) * 4 > kFuseLds)) Q >>= 1;
     if (fused_tile_words(P.n, P.det_lanes, P.m[0], Q) * 4 > kFuseLds) {
@@ -335,8 +343,10 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     }
   }
   // Left-looking elimination (one lane per matrix, pivot rows only in registers) on request
-  // (flag bit 2) up to kLLMaxN; the exchanging kernel alone by default (bit 3).
-  if (P.fused && (flags & 4u) && !(flags & 8u)) P.det_ll = s.n <= kLLMaxN;
+  // (flag bit 2) up to kLLMaxN, or where the table chose it; the exchanging kernel alone by
+  // default and with flag bit 3.
+  const bool want_ll = (flags & 4u) || (!(flags & 8u) && tune.left_looking[tclass][P.n] == 1);
+  if (P.fused && want_ll && !(flags & 8u)) P.det_ll = s.n <= kLLMaxN;
   if (P.fused) {
     // the pre-tensor is the output of the evaluation pass over variable 1 (pass index
     // k - 2 counting from the last variable; passes alternate tmpA, tmpB), or the residues
@@ -363,6 +373,16 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   P.out_bytes = (size_t)P.C * P.L * 4;
   *out = std::move(P);
   return "";
+}
+
+void set_tuning(const Tuning& t) {
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  g_tuning = t;
+}
+
+Tuning get_tuning() {
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  return g_tuning;
 }
 
 int upload_tables(Plan* plan) {

@@ -41,6 +41,16 @@ PD_HD size_t fused_tile_words(int n, int lanes, int m0, int Q) {
   return (size_t)((n * ncp) | 1) * m0 * Q;
 }
 
+// Launch-mapping table (polydet_tuning): [class][n], 0 = built-in choice. Class 0 is a first
+// variable with 2..4 coefficients (paired evaluation), class 1 every other fused matrix.
+struct Tuning {
+  int lanes[2][kMaxN + 1] = {};
+  int left_looking[2][kMaxN + 1] = {};
+  int tile_points[2][kMaxN + 1] = {};
+};
+void set_tuning(const Tuning& t);
+Tuning get_tuning();
+
 // The descending table of primes p in (2^30, 2^31) with p = 1 mod 2^16.
 const std::vector<uint32_t>& prime_table();
 uint32_t primitive_root(uint32_t p);

@@ -430,6 +430,45 @@ const char* polydet_status_string(polydet_status status) {
 
 const char* polydet_last_error(void) { return g_last_error.c_str(); }
 
+static_assert(POLYDET_TUNE_ORDERS == pd::kMaxN + 1, "tuning table covers orders 0..kMaxN");
+
+polydet_status polydet_set_tuning(const polydet_tuning* table) {
+  pd::Tuning t;
+  if (table) {
+    for (int c = 0; c < 2; ++c) {
+      for (int n = 0; n <= pd::kMaxN; ++n) {
+        const int lanes = table->lanes[c][n], ll = table->left_looking[c][n];
+        const int q = table->tile_points[c][n];
+        const bool pow2q = q == 0 || q == 1 || q == 2 || q == 4 || q == 8 || q == 16;
+        if (n == 0 && (lanes || ll || q)) return fail(POLYDET_EINVAL, "tuning: order 0 is unused");
+        if (lanes != 0 && !pd::det_config_supported(n, lanes))
+          return fail(POLYDET_EINVAL, "tuning: lanes per matrix not compiled for this order");
+        if (ll < 0 || ll > 2 || (ll == 1 && n > pd::kLLMaxN))
+          return fail(POLYDET_EINVAL, "tuning: left_looking must be 0, 1 (n <= 16) or 2");
+        if (!pow2q) return fail(POLYDET_EINVAL, "tuning: tile_points must be 0, 1, 2, 4, 8 or 16");
+        t.lanes[c][n] = lanes;
+        t.left_looking[c][n] = ll;
+        t.tile_points[c][n] = q;
+      }
+    }
+  }
+  pd::set_tuning(t);
+  return POLYDET_OK;
+}
+
+polydet_status polydet_get_tuning(polydet_tuning* out) {
+  if (!out) return fail(POLYDET_EINVAL, "tuning: null output");
+  const pd::Tuning t = pd::get_tuning();
+  for (int c = 0; c < 2; ++c) {
+    for (int n = 0; n < POLYDET_TUNE_ORDERS; ++n) {
+      out->lanes[c][n] = n <= pd::kMaxN ? t.lanes[c][n] : 0;
+      out->left_looking[c][n] = n <= pd::kMaxN ? t.left_looking[c][n] : 0;
+      out->tile_points[c][n] = n <= pd::kMaxN ? t.tile_points[c][n] : 0;
+    }
+  }
+  return POLYDET_OK;
+}
+
 void polydet_limits(int32_t* max_n, int32_t* max_vars, int32_t* max_grid_per_var,
                     int32_t* max_primes) {
   if (max_n) *max_n = pd::kMaxN;

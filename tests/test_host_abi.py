@@ -185,7 +185,16 @@ def test_structural_row_order():
     assert info["row_order"] == tuple(range(5)) and info["det_sign"] == 1
 
 
-def test_elimination_form_choice():
+@pytest.fixture
+def builtin_tuning():
+    """The library's built-in launch mapping for the test, the installed table after it."""
+    saved = pdm.get_tuning()
+    pdm.set_tuning(None)
+    yield
+    pdm.set_tuning(saved)
+
+
+def test_elimination_form_choice(builtin_tuning):
     # the exchanging kernel alone by default; a left-looking pass on request for orders up
     # to 16 when the first variable is evaluated inside the elimination kernel
     H = pdm.HOST_ONLY
@@ -210,3 +219,49 @@ def test_serving_jobs_compare_by_identity():
     running.remove(jobs[2])
     running.remove(jobs[0])
     assert running == [jobs[1]]
+
+
+def test_tuning_table_round_trip_and_effect(builtin_tuning):
+    H = pdm.HOST_ONLY
+    table = {"lanes": {"paired": {"12": 2, "20": 8}, "other": {"12": 4}},
+             "left_looking": {"paired": {"9": 1}, "other": {"12": 2}},
+             "tile_points": {"paired": {"12": 4}, "other": {}}}
+    pdm.set_tuning(table)
+    got = pdm.get_tuning()
+    assert got["lanes"] == {"paired": {12: 2, 20: 8}, "other": {12: 4}}
+    assert got["left_looking"] == {"paired": {9: 1}, "other": {12: 2}}
+    assert got["tile_points"] == {"paired": {12: 4}, "other": {}}
+    # class "paired": 2..4 coefficients in the first variable; "other": everything else
+    assert pdm.plan(12, (3, 2), coeff_bits=8, flags=H).info["det_lanes"] == 2
+    assert pdm.plan(12, (4, 2), coeff_bits=8, flags=H).info["det_lanes"] == 4
+    assert pdm.plan(12, (0, 2), coeff_bits=8, flags=H).info["det_lanes"] == 4
+    assert pdm.plan(20, (1, 1), coeff_bits=8, flags=H).info["det_lanes"] == 8
+    assert pdm.plan(11, (1, 1), coeff_bits=8, flags=H).info["det_lanes"] == 1  # no entry
+    assert pdm.plan(9, (2,), coeff_bits=8, flags=H).info["det_left_looking"] == 1
+    assert pdm.plan(9, (5,), coeff_bits=8, flags=H).info["det_left_looking"] == 0
+    # flags override the table
+    pl = pdm.plan(12, (3, 2), coeff_bits=8, flags=H | pdm.DET_LANES_LOG2(0))
+    assert pl.info["det_lanes"] == 1
+    assert pdm.plan(9, (2,), coeff_bits=8,
+                    flags=H | pdm.DET_EXCHANGE).info["det_left_looking"] == 0
+    pdm.set_tuning(None)
+    assert pdm.get_tuning()["lanes"] == {"paired": {}, "other": {}}
+    assert pdm.plan(12, (3, 2), coeff_bits=8, flags=H).info["det_lanes"] == 1
+
+
+@pytest.mark.parametrize("bad", [
+    {"lanes": {"paired": {"13": 1}}},          # one lane per matrix only up to n = 12
+    {"lanes": {"other": {"4": 16}}},            # 16 lanes only from n = 16
+    {"lanes": {"paired": {"8": 3}}},
+    {"left_looking": {"paired": {"17": 1}}},    # left-looking only up to n = 16
+    {"left_looking": {"other": {"5": 3}}},
+    {"tile_points": {"paired": {"5": 3}}},
+    {"tile_points": {"paired": {"5": 32}}},
+    {"lanes": {"paired": {"0": 1}}},
+])
+def test_tuning_table_rejects_bad_entries(builtin_tuning, bad):
+    before = pdm.get_tuning()
+    with pytest.raises(pdm.PolydetError) as e:
+        pdm.set_tuning(bad)
+    assert e.value.status == B.EINVAL
+    assert pdm.get_tuning() == before  # no change
