@@ -27,6 +27,9 @@ FLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",
     # no packed-fp32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the elimination kernels rely on full unrolling (static register indices); at n = 32
+    # the unrolled body is larger than the default limit of the unroll pragma
+    "-mllvm", "-pragma-unroll-threshold=200000",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wno-unused-command-line-argument",
 ]

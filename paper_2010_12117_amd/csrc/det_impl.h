@@ -32,14 +32,68 @@ constexpr int kEvalChunk = 8;  // entries per scheduling window of the fused eva
 // group holds columns t, t + GL, t + 2 GL, ... of all n rows in registers (a[c][i] is
 // A[i][c GL + t]), so every index below is static after unrolling. The owner of column k
 // (lane k mod GL) finds the pivot row and broadcasts the row index, the pivot and the
-// multipliers to its group with lane shuffles; row exchanges are register selects.
+// multipliers to its group with DPP moves; row exchanges are register selects.
 // ------------------------------------------------------------------------------------
+
+// Lane `src` of each aligned group of GL lanes to the whole group, as DPP moves (VALU, no
+// LDS round trip). `src` is a constant after unrolling, so each switch folds to one case.
+// GL = 2, 4: quad_perm within each quad. GL = 16: row_newbcast (lane src of each 16-lane
+// row). GL = 8: row_newbcast of lane src into lanes 0-7 of the row (banks 0-1), then of lane
+// 8 + src into lanes 8-15 (banks 2-3). Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+}
+template <int O>
+__device__ __forceinline__ uint32_t bcast8(uint32_t v) {
+  const int lo = __builtin_amdgcn_update_dpp((int)v, (int)v, 0x150 + O, 0xF, 0x3, false);
+  return (uint32_t)__builtin_amdgcn_update_dpp(lo, (int)v, 0x158 + O, 0xF, 0xC, false);
+}
+
 template <int GL>
 __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
   if constexpr (GL == 1) {
     return v;
+  } else if constexpr (GL == 2) {
+    return src == 0 ? dpp_mov<0xA0>(v) : dpp_mov<0xF5>(v);  // [0,0,2,2] / [1,1,3,3]
+  } else if constexpr (GL == 4) {
+    switch (src) {
+      case 0: return dpp_mov<0x00>(v);
+      case 1: return dpp_mov<0x55>(v);
+      case 2: return dpp_mov<0xAA>(v);
+      default: return dpp_mov<0xFF>(v);
+    }
+  } else if constexpr (GL == 8) {
+    switch (src) {
+      case 0: return bcast8<0>(v);
+      case 1: return bcast8<1>(v);
+      case 2: return bcast8<2>(v);
+      case 3: return bcast8<3>(v);
+      case 4: return bcast8<4>(v);
+      case 5: return bcast8<5>(v);
+      case 6: return bcast8<6>(v);
+      default: return bcast8<7>(v);
+    }
   } else {
-    return (uint32_t)__shfl((int)v, src, GL);
+    static_assert(GL == 16, "lane groups of 1, 2, 4, 8 or 16");
+    switch (src) {
+      case 0: return dpp_mov<0x150>(v);
+      case 1: return dpp_mov<0x151>(v);
+      case 2: return dpp_mov<0x152>(v);
+      case 3: return dpp_mov<0x153>(v);
+      case 4: return dpp_mov<0x154>(v);
+      case 5: return dpp_mov<0x155>(v);
+      case 6: return dpp_mov<0x156>(v);
+      case 7: return dpp_mov<0x157>(v);
+      case 8: return dpp_mov<0x158>(v);
+      case 9: return dpp_mov<0x159>(v);
+      case 10: return dpp_mov<0x15A>(v);
+      case 11: return dpp_mov<0x15B>(v);
+      case 12: return dpp_mov<0x15C>(v);
+      case 13: return dpp_mov<0x15D>(v);
+      case 14: return dpp_mov<0x15E>(v);
+      default: return dpp_mov<0x15F>(v);
+    }
   }
 }
 
@@ -292,6 +346,10 @@ __device__ __forceinline__ void det_fused_body(
             const auto eo = __builtin_amdgcn_permlane32_swap(v, v, false, false);
             a[c][i] = fold(eo[0] + (eo[1] ^ sm) + sc, p);
           }
+          // without a branch per entry (GL > 1) the scheduler would run every product first
+          // and keep all of them live until their exchanges: bound its window
+          if (GL > 1 && (c * N + i) % kEvalChunk == kEvalChunk - 1)
+            __builtin_amdgcn_sched_barrier(0);
         }
       }
     } else {
