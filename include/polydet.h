@@ -140,6 +140,9 @@ typedef struct polydet_plan_info {
    * refer to the reordered matrix, whose determinant is det_sign times det M. */
   uint8_t row_order[32];
   int32_t det_left_looking; /* 1 if a left-looking pass runs before the exchanging kernel */
+  int32_t prime_group;      /* primes per pass of S1-S4 (pn unless the workspace is capped) */
+  size_t coef_bytes;        /* 4 * pn * ncoeff: the coefficient residues at off_coef, prime
+                             * major ([pn][ncoeff], Montgomery form, factor G left in) */
 } polydet_plan_info;
 
 typedef struct polydet_plan_s* polydet_plan_t;
@@ -153,6 +156,18 @@ typedef struct polydet_plan_s* polydet_plan_t;
  * The plan's tables live on the device that is current when it is built. */
 polydet_status polydet_plan(const polydet_shape* shape, const int64_t* host_coeffs,
                             uint32_t flags, polydet_plan_t* out);
+
+/* polydet_plan with a cap on the workspace of one solve (bytes; 0: no cap). When the solve
+ * of all pn primes at once needs more, the plan takes the primes in groups of
+ * info.prime_group, the largest that fits: S1-S4 (reduce, evaluation, determinants,
+ * interpolation) run group by group on the stream, each group leaving its coefficient
+ * residues in the workspace, and the reconstruction runs once at the end (the paper solves
+ * one prime at a time; Algorithm 1). Results are identical to the uncapped plan.
+ * EUNSUPPORTED if even one prime does not fit; EINVAL with POLYDET_STAGE_TIMING when the cap
+ * splits the primes. */
+polydet_status polydet_plan_capped(const polydet_shape* shape, const int64_t* host_coeffs,
+                                   uint32_t flags, size_t max_workspace_bytes,
+                                   polydet_plan_t* out);
 
 /* Build one plan for `count` matrices of possibly different shapes, solved together by
  * polydet_solve_batch. host_coeffs: NULL or an array of `count` host pointers (each may be
@@ -187,6 +202,24 @@ polydet_status polydet_solve_batch(polydet_plan_t plan, const int64_t* d_coeffs,
                                    const int64_t* coeff_offsets, uint32_t* d_out,
                                    const int64_t* out_offsets, void* d_workspace,
                                    size_t workspace_bytes, void* stream);
+
+/* The solve of a single-matrix plan in two parts, for callers that checkpoint, resume or
+ * cancel long solves between primes:
+ *   polydet_solve_primes runs S1-S4 for primes [prime_begin, prime_end) (0 <= begin < end
+ *   <= pn; any split) and leaves their coefficient residues at workspace offset
+ *   info.off_coef + 4 * ncoeff * i for prime i; it does not touch the other primes' slots.
+ *   polydet_reconstruct runs S5 (Section 3.4, Algorithm 4) from the slots of all pn primes
+ *   and writes the output limbs as polydet_solve does.
+ * Calling polydet_solve_primes for every prime, in any order and in any number of calls,
+ * then polydet_reconstruct, gives exactly polydet_solve's result. The coefficient region
+ * (info.coef_bytes at info.off_coef) is all the state between calls: a caller may copy it
+ * out after some primes, and later copy it into another workspace and go on with the rest.
+ * Both are asynchronous on `stream`; argument errors are EINVAL (batch plans included). */
+polydet_status polydet_solve_primes(polydet_plan_t plan, const int64_t* d_coeffs,
+                                    int32_t prime_begin, int32_t prime_end, void* d_workspace,
+                                    size_t workspace_bytes, void* stream);
+polydet_status polydet_reconstruct(polydet_plan_t plan, void* d_workspace,
+                                   size_t workspace_bytes, uint32_t* d_out, void* stream);
 
 /* Device time per stage of the solves of a plan made with POLYDET_STAGE_TIMING (the
  * paper's tables report the same split: FFT, DET, IFFT, CRT). Waits for the recorded

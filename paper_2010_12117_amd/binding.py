@@ -63,7 +63,8 @@ class PlanInfo(ctypes.Structure):
                 ("in_bytes", ctypes.c_size_t), ("out_bytes", ctypes.c_size_t),
                 ("workspace_bytes", ctypes.c_size_t), ("off_eval", ctypes.c_size_t),
                 ("off_detv", ctypes.c_size_t), ("off_coef", ctypes.c_size_t),
-                ("row_order", ctypes.c_uint8 * 32), ("det_left_looking", ctypes.c_int32)]
+                ("row_order", ctypes.c_uint8 * 32), ("det_left_looking", ctypes.c_int32),
+                ("prime_group", ctypes.c_int32), ("coef_bytes", ctypes.c_size_t)]
 
 
 TUNE_ORDERS = 33
@@ -79,7 +80,8 @@ class Tuning(ctypes.Structure):
 EXPORTS = ["polydet_plan", "polydet_plan_batch", "polydet_plan_query", "polydet_plan_primes",
            "polydet_solve", "polydet_solve_batch", "polydet_plan_destroy",
            "polydet_status_string", "polydet_last_error", "polydet_limits",
-           "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning"]
+           "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning",
+           "polydet_plan_capped", "polydet_solve_primes", "polydet_reconstruct"]
 
 _lib = None
 
@@ -120,9 +122,13 @@ def load_library(path: str = LIB_PATH):
     lib.polydet_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), P64]
     lib.polydet_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.polydet_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.polydet_plan_capped.argtypes = [ctypes.POINTER(Shape), vp, u32, sz, ctypes.POINTER(vp)]
+    lib.polydet_solve_primes.argtypes = [vp, vp, i32, i32, vp, sz, vp]
+    lib.polydet_reconstruct.argtypes = [vp, vp, sz, vp, vp]
     for name in ["polydet_plan", "polydet_plan_batch", "polydet_plan_query",
                  "polydet_plan_primes", "polydet_solve", "polydet_solve_batch",
-                 "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning"]:
+                 "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning",
+                 "polydet_plan_capped", "polydet_solve_primes", "polydet_reconstruct"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     _install_default_tuning()
@@ -260,7 +266,9 @@ class Plan:
 
 
 def plan(n: int, deg: Sequence[int], host_coeffs: Optional[np.ndarray] = None,
-         coeff_bits: Optional[int] = None, flags: int = 0) -> Plan:
+         coeff_bits: Optional[int] = None, flags: int = 0,
+         max_workspace: Optional[int] = None) -> Plan:
+    """polydet_plan, or polydet_plan_capped when max_workspace (bytes) is given."""
     lib = load_library()
     if coeff_bits is None:
         coeff_bits = coeff_bits_of(host_coeffs) if host_coeffs is not None else 63
@@ -270,7 +278,11 @@ def plan(n: int, deg: Sequence[int], host_coeffs: Optional[np.ndarray] = None,
     if host_coeffs is not None:
         host_coeffs = np.ascontiguousarray(host_coeffs, dtype=np.int64)
         ptr = host_coeffs.ctypes.data_as(ctypes.c_void_p)
-    _check(lib.polydet_plan(ctypes.byref(s), ptr, flags, ctypes.byref(h)))
+    if max_workspace is None:
+        _check(lib.polydet_plan(ctypes.byref(s), ptr, flags, ctypes.byref(h)))
+    else:
+        _check(lib.polydet_plan_capped(ctypes.byref(s), ptr, flags, int(max_workspace),
+                                       ctypes.byref(h)))
     return Plan(h, 1)
 
 
@@ -324,6 +336,44 @@ def solve_device(pl: Plan, d_coeffs, d_out=None, workspace=None, stream=None):
                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                              _stream_ptr(torch, stream)))
     return d_out, workspace
+
+
+def solve_primes_device(pl: Plan, d_coeffs, prime_begin: int, prime_end: int, workspace,
+                        stream=None):
+    """Enqueue polydet_solve_primes: S1-S4 for primes [prime_begin, prime_end), leaving their
+    coefficient residues in the workspace's coefficient region."""
+    torch = _torch()
+    info = pl.info
+    if d_coeffs.dtype != torch.int64 or not d_coeffs.is_cuda or not d_coeffs.is_contiguous():
+        raise ValueError("coefficients must be a contiguous int64 device tensor")
+    if d_coeffs.numel() * 8 != info["in_bytes"]:
+        raise ValueError("coefficient tensor size does not match the plan")
+    lib = load_library()
+    _check(lib.polydet_solve_primes(pl.handle, ctypes.c_void_p(d_coeffs.data_ptr()),
+                                    int(prime_begin), int(prime_end),
+                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                    _stream_ptr(torch, stream)))
+
+
+def reconstruct_device(pl: Plan, workspace, d_out=None, stream=None):
+    """Enqueue polydet_reconstruct (S5) from the coefficient residues of all primes."""
+    torch = _torch()
+    info = pl.info
+    if d_out is None:
+        d_out = torch.empty((info["ncoeff"], info["limbs"]), dtype=torch.int32,
+                            device=workspace.device)
+    lib = load_library()
+    _check(lib.polydet_reconstruct(pl.handle, ctypes.c_void_p(workspace.data_ptr()),
+                                   workspace.numel(), ctypes.c_void_p(d_out.data_ptr()),
+                                   _stream_ptr(torch, stream)))
+    return d_out
+
+
+def coefficient_region(pl: Plan, workspace):
+    """The workspace bytes that hold the coefficient residues (the state between calls of
+    solve_primes_device), as a view."""
+    info = pl.info
+    return workspace[info["off_coef"]:info["off_coef"] + info["coef_bytes"]]
 
 
 def solve_batch_device(pl: Plan, d_coeffs, coeff_offsets: Sequence[int], d_out,

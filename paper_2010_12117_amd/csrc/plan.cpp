@@ -121,7 +121,7 @@ static int default_det_lanes(int n) {
 }
 
 std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t flags,
-                          MatPlan* out, bool* unsupported) {
+                          size_t max_ws, MatPlan* out, bool* unsupported) {
   *unsupported = false;
   MatPlan P;
   if (s.n < 1) return "matrix order n must be >= 1";
@@ -298,15 +298,17 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     P.det_lanes = want;
   }
 
-  // workspace layout
-  const size_t pn = P.pn;
+  // Workspace layout for pg primes at a time: every per-prime region holds pg primes, the
+  // coefficient residues (S4's output, S5's input) all pn. pg < pn only when the caller caps
+  // the workspace (max_ws): S1-S4 then run group by group.
+  auto layout = [&](size_t pg) -> size_t {
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = align256(off + bytes);
     return o;
   };
-  P.off_res = take(pn * P.nent * P.T * 4);
+  P.off_res = take(pg * P.nent * P.T * 4);
   // forward passes run over the last variable first; the output of pass v has shape
   // [pn*nent][prod_{u<v} m_u][prod_{u>=v} N_u]
   size_t inter = 0;
@@ -316,8 +318,8 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     for (int u = v; u < s.k; ++u) sz *= P.N[u];
     inter = std::max(inter, (size_t)sz);
   }
-  P.off_tmpA = take(pn * P.nent * inter * 4);
-  P.off_tmpB = take(pn * P.nent * inter * 4);
+  P.off_tmpA = take(pg * P.nent * inter * 4);
+  P.off_tmpB = take(pg * P.nent * inter * 4);
   // Fused evaluation of the first variable inside the elimination kernel: a block stages
   // Q points of every entry (m0 coefficients each) in LDS, at most kFuseLds bytes, and
   // handles S values of the first variable's grid index.
@@ -334,7 +336,7 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
       P.fused = false;  // the tile does not fit: evaluate in full, then eliminate
     } else {
       const int J = per_block / Q;
-      const int64_t base_blocks = (int64_t)P.pn * ((R + Q - 1) / Q);
+      const int64_t base_blocks = (int64_t)pg * ((R + Q - 1) / Q);
       // enough blocks to fill 256 CUs several times; each block reuses its tile S / J times
       int iters = (int)std::max<int64_t>(1, (int64_t)NJ * base_blocks / (2048LL * J));
       iters = std::min(iters, std::max(1, (NJ + J - 1) / J));
@@ -346,17 +348,17 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   // (flag bit 2) up to kLLMaxN, or where the table chose it; the exchanging kernel alone by
   // default and with flag bit 3.
   const bool want_ll = (flags & 4u) || (!(flags & 8u) && tune.left_looking[tclass][P.n] == 1);
-  if (P.fused && want_ll && !(flags & 8u)) P.det_ll = s.n <= kLLMaxN;
+  P.det_ll = P.fused && want_ll && !(flags & 8u) && s.n <= kLLMaxN;
   if (P.fused) {
     // the pre-tensor is the output of the evaluation pass over variable 1 (pass index
     // k - 2 counting from the last variable; passes alternate tmpA, tmpB), or the residues
     P.off_pre = s.k == 1 ? P.off_res : ((s.k - 2) % 2 == 0 ? P.off_tmpA : P.off_tmpB);
     P.off_eval = SIZE_MAX;
   } else {
-    P.off_eval = s.k == 0 ? P.off_res : take(pn * P.nent * P.G * 4);
+    P.off_eval = s.k == 0 ? P.off_res : take(pg * P.nent * P.G * 4);
   }
-  P.off_detv = take(pn * P.G * 4);
-  P.off_den = take(pn * P.G * 4);
+  P.off_detv = take(pg * P.G * 4);
+  P.off_den = take(pg * P.G * 4);
   // interpolation passes run over the first variable first, trimming N_v to D_v + 1
   size_t iinter = 0;
   for (int v = 0; v + 1 < s.k; ++v) {
@@ -365,14 +367,48 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     for (int u = v + 1; u < s.k; ++u) sz *= P.N[u];
     iinter = std::max(iinter, (size_t)sz);
   }
-  P.off_iA = take(pn * iinter * 4);
-  P.off_iB = take(pn * iinter * 4);
-  P.off_coef = s.k == 0 ? P.off_detv : take(pn * P.C * 4);
-  P.ws_bytes = std::max<size_t>(off, 256);
+  P.off_iA = take(pg * iinter * 4);
+  P.off_iB = take(pg * iinter * 4);
+  P.off_coef = s.k == 0 ? P.off_detv : take((size_t)P.pn * P.C * 4);
+  return std::max<size_t>(off, 256);
+  };
+  P.prime_group = P.pn;
+  P.ws_bytes = layout(P.pn);
+  if (max_ws > 0 && P.ws_bytes > max_ws) {
+    // the largest group of primes whose solve fits (integer matrices are never split: their
+    // one point per prime costs nothing)
+    int g = s.k == 0 ? 0 : P.pn - 1;
+    while (g >= 1 && layout(g) > max_ws) --g;
+    if (g < 1) {
+      *unsupported = true;
+      return "the workspace cap is below the footprint of a solve one prime at a time";
+    }
+    P.prime_group = g;
+    P.ws_bytes = layout(g);
+  }
   P.in_bytes = (size_t)P.nent * P.T * 8;
   P.out_bytes = (size_t)P.C * P.L * 4;
   *out = std::move(P);
   return "";
+}
+
+MatPlan prime_range_plan(const MatPlan& P, int b, int e) {
+  MatPlan R = P;
+  R.pn = e - b;
+  R.d_pc = P.d_pc + b;
+  for (int v = 0; v < P.k; ++v) {
+    R.tw_off[v] = P.tw_off[v] + (int64_t)b * P.tw_stride;
+  }
+  if (P.k == 0) {
+    // an integer matrix: the determinant of prime i is its coefficient residue, at slot i of
+    // regions that hold all pn primes
+    R.off_detv = P.off_detv + (size_t)b * 4;
+    R.off_den = P.off_den + (size_t)b * 4;
+    R.off_coef = R.off_detv;
+  } else {
+    R.off_coef = P.off_coef + (size_t)b * P.C * 4;
+  }
+  return R;
 }
 
 void set_tuning(const Tuning& t) {

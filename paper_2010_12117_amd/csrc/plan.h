@@ -61,6 +61,7 @@ struct MatPlan {
   int deg[kMaxVars] = {0}, D[kMaxVars] = {0}, N[kMaxVars] = {0}, m[kMaxVars] = {0};
   int64_t G = 1, C = 1, T = 1, nent = 0;
   int pn = 0, L = 0, prime_off = 0, det_lanes = 1;
+  int prime_group = 0;  // primes per S1-S4 pass (pn unless the workspace is capped)
   std::vector<uint32_t> primes;
   std::vector<PrimeConst> pc;
   std::vector<uint8_t> entry_zero;  // empty when the plan was built without coefficients
@@ -112,10 +113,16 @@ struct ShapeIn {
   int coeff_bits;
 };
 
-// Fills everything host-side (no device work). Returns an empty string on success or an
+// Fills everything host-side (no device work). max_ws > 0 caps the workspace of one solve
+// (primes are then taken in groups of prime_group). Returns an empty string on success or an
 // error message; *unsupported tells EUNSUPPORTED from EINVAL.
 std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t flags,
-                          MatPlan* out, bool* unsupported);
+                          size_t max_ws, MatPlan* out, bool* unsupported);
+
+// The plan of primes [b, e) of P: the same tables offset to prime b, pn = e - b, the
+// per-prime workspace regions of a group, and the coefficient residues written at prime b's
+// slot of P's coefficient region. Only S1-S4 may run on it.
+MatPlan prime_range_plan(const MatPlan& P, int b, int e);
 
 // Serialises the device tables of every matrix, uploads them in one allocation and sets
 // the d_* pointers. Returns a HIP error code (0 = success).

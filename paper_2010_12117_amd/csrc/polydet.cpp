@@ -97,7 +97,7 @@ polydet_status make_batch(polydet_plan_s* h, uint32_t flags) {
 
 polydet_status make_plan(const polydet_shape* shapes, int32_t count,
                          const int64_t* const* host_coeffs, uint32_t flags, bool batch,
-                         polydet_plan_t* out) {
+                         size_t max_ws, polydet_plan_t* out) {
   if (!out) return fail(POLYDET_EINVAL, "output plan pointer is NULL");
   *out = nullptr;
   if (!shapes || count < 1) return fail(POLYDET_EINVAL, "need at least one shape");
@@ -114,7 +114,10 @@ polydet_status make_plan(const polydet_shape* shapes, int32_t count,
     }
     bool unsupported = false;
     const int64_t* hc = host_coeffs ? host_coeffs[i] : nullptr;
-    std::string err = pd::build_matplan(s, hc, flags, &h->plan.mats[i], &unsupported);
+    std::string err = pd::build_matplan(s, hc, flags, max_ws, &h->plan.mats[i], &unsupported);
+    if (err.empty() && (flags & POLYDET_STAGE_TIMING) &&
+        h->plan.mats[i].prime_group < h->plan.mats[i].pn)
+      err = "stage timing needs a plan that solves all primes at once (no workspace cap)";
     if (err.empty() && !pd::det_config_supported(s.n, h->plan.mats[i].det_lanes)) {
       unsupported = true;
       err = "no elimination kernel for this order and lane count";
@@ -186,8 +189,31 @@ hipError_t harvest(StageTimer* T, int slot) {
   return hipSuccess;
 }
 
+// S1-S4 for primes [b, e), prime_group at a time; each group leaves its coefficient residues
+// in the coefficient region.
+polydet_status run_primes(const pd::MatPlan& P, const int64_t* d_coeffs, int b, int e,
+                          uint8_t* ws, hipStream_t st) {
+  hipError_t err;
+  const int g = P.prime_group > 0 ? P.prime_group : P.pn;
+  for (int lo = b; lo < e; lo += g) {
+    const pd::MatPlan R = pd::prime_range_plan(P, lo, std::min(e, lo + g));
+    if ((err = pd::run_reduce(R, d_coeffs, ws, st)) != hipSuccess) return hip_fail(err, "reduce");
+    if ((err = pd::run_evaluate(R, ws, st)) != hipSuccess) return hip_fail(err, "evaluate");
+    if ((err = pd::run_det(R, ws, st)) != hipSuccess) return hip_fail(err, "determinants");
+    if ((err = pd::run_finalize(R, ws, st)) != hipSuccess) return hip_fail(err, "finalize");
+    if ((err = pd::run_interpolate(R, ws, st)) != hipSuccess) return hip_fail(err, "interpolate");
+  }
+  return POLYDET_OK;
+}
+
 polydet_status run_one(const pd::MatPlan& P, const int64_t* d_coeffs, uint32_t* d_out,
                        uint8_t* ws, hipStream_t st, StageTimer* T) {
+  if (P.prime_group < P.pn) {  // capped workspace: S1-S4 by prime groups, then S5
+    polydet_status s = run_primes(P, d_coeffs, 0, P.pn, ws, st);
+    if (s != POLYDET_OK) return s;
+    hipError_t e = pd::run_reconstruct(P, ws, d_out, st);
+    return e == hipSuccess ? POLYDET_OK : hip_fail(e, "reconstruct");
+  }
   hipError_t e;
   hipEvent_t* ev = nullptr;
   if (T) {
@@ -232,13 +258,20 @@ extern "C" {
 polydet_status polydet_plan(const polydet_shape* shape, const int64_t* host_coeffs,
                             uint32_t flags, polydet_plan_t* out) {
   const int64_t* hc[1] = {host_coeffs};
-  return make_plan(shape, 1, hc, flags, false, out);
+  return make_plan(shape, 1, hc, flags, false, 0, out);
+}
+
+polydet_status polydet_plan_capped(const polydet_shape* shape, const int64_t* host_coeffs,
+                                   uint32_t flags, size_t max_workspace_bytes,
+                                   polydet_plan_t* out) {
+  const int64_t* hc[1] = {host_coeffs};
+  return make_plan(shape, 1, hc, flags, false, max_workspace_bytes, out);
 }
 
 polydet_status polydet_plan_batch(const polydet_shape* shapes, int32_t count,
                                   const int64_t* const* host_coeffs, uint32_t flags,
                                   polydet_plan_t* out) {
-  return make_plan(shapes, count, host_coeffs, flags, true, out);
+  return make_plan(shapes, count, host_coeffs, flags, true, 0, out);
 }
 
 polydet_status polydet_plan_query(polydet_plan_t plan, int32_t index, polydet_plan_info* out) {
@@ -262,6 +295,8 @@ polydet_status polydet_plan_query(polydet_plan_t plan, int32_t index, polydet_pl
   out->det_sign = P.det_sign;
   for (int i = 0; i < P.n && i < 32; ++i) out->row_order[i] = (uint8_t)P.row_order[i];
   out->det_left_looking = P.det_ll ? 1 : 0;
+  out->prime_group = P.prime_group;
+  out->coef_bytes = (size_t)P.pn * P.C * 4;
   out->in_bytes = P.in_bytes;
   out->out_bytes = P.out_bytes;
   out->workspace_bytes = plan->plan.batch ? plan->plan.ws_bytes : P.ws_bytes;
@@ -292,6 +327,39 @@ polydet_status polydet_solve(polydet_plan_t plan, const int64_t* d_coeffs, uint3
   polydet_status st = check_device(plan->plan);
   if (st != POLYDET_OK) return st;
   return run_one(P, d_coeffs, d_out, (uint8_t*)d_workspace, (hipStream_t)stream, plan->timer);
+}
+
+static polydet_status check_single(polydet_plan_t plan, void* d_workspace,
+                                   size_t workspace_bytes) {
+  if (!plan) return fail(POLYDET_EINVAL, "NULL plan");
+  if (plan->plan.batch) return fail(POLYDET_EINVAL, "a batch plan cannot be solved by ranges");
+  if (!d_workspace) return fail(POLYDET_EINVAL, "NULL workspace");
+  if (workspace_bytes < plan->plan.mats[0].ws_bytes) return fail(POLYDET_EINVAL, "workspace too small");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(POLYDET_EINVAL, "workspace must be 256-byte aligned");
+  return check_device(plan->plan);
+}
+
+polydet_status polydet_solve_primes(polydet_plan_t plan, const int64_t* d_coeffs,
+                                    int32_t prime_begin, int32_t prime_end, void* d_workspace,
+                                    size_t workspace_bytes, void* stream) {
+  polydet_status st = check_single(plan, d_workspace, workspace_bytes);
+  if (st != POLYDET_OK) return st;
+  const pd::MatPlan& P = plan->plan.mats[0];
+  if (!d_coeffs) return fail(POLYDET_EINVAL, "NULL coefficients");
+  if (prime_begin < 0 || prime_end > P.pn || prime_begin >= prime_end)
+    return fail(POLYDET_EINVAL, "prime range must satisfy 0 <= begin < end <= pn");
+  return run_primes(P, d_coeffs, prime_begin, prime_end, (uint8_t*)d_workspace,
+                    (hipStream_t)stream);
+}
+
+polydet_status polydet_reconstruct(polydet_plan_t plan, void* d_workspace,
+                                   size_t workspace_bytes, uint32_t* d_out, void* stream) {
+  polydet_status st = check_single(plan, d_workspace, workspace_bytes);
+  if (st != POLYDET_OK) return st;
+  if (!d_out) return fail(POLYDET_EINVAL, "NULL output");
+  hipError_t e = pd::run_reconstruct(plan->plan.mats[0], (uint8_t*)d_workspace, d_out,
+                                     (hipStream_t)stream);
+  return e == hipSuccess ? POLYDET_OK : hip_fail(e, "reconstruct");
 }
 
 static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,

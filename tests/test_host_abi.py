@@ -265,3 +265,52 @@ def test_tuning_table_rejects_bad_entries(builtin_tuning, bad):
         pdm.set_tuning(bad)
     assert e.value.status == B.EINVAL
     assert pdm.get_tuning() == before  # no change
+
+
+def test_capped_workspace_groups_primes():
+    H = pdm.HOST_ONLY
+    arr = W.config2()
+    full = pdm.plan(12, (3, 3, 3), host_coeffs=arr, flags=H).info
+    assert full["prime_group"] == full["pn"] == 7
+    assert full["coef_bytes"] == 4 * full["pn"] * full["ncoeff"]
+    seen = set()
+    for frac in (0.9, 0.6, 0.4, 0.25):
+        cap = int(full["workspace_bytes"] * frac)
+        info = pdm.plan(12, (3, 3, 3), host_coeffs=arr, flags=H, max_workspace=cap).info
+        assert info["workspace_bytes"] <= cap
+        assert 1 <= info["prime_group"] < info["pn"]
+        # the largest group that fits: one more prime would not
+        seen.add(info["prime_group"])
+        assert info["pn"] == full["pn"] and info["coef_bytes"] == full["coef_bytes"]
+    assert len(seen) >= 3
+    # no cap needed: the plan is the uncapped one
+    info = pdm.plan(12, (3, 3, 3), host_coeffs=arr, flags=H,
+                    max_workspace=full["workspace_bytes"]).info
+    assert info["prime_group"] == 7 and info["workspace_bytes"] == full["workspace_bytes"]
+    # below one prime's footprint
+    with pytest.raises(pdm.PolydetError) as e:
+        pdm.plan(12, (3, 3, 3), host_coeffs=arr, flags=H, max_workspace=1 << 20)
+    assert e.value.status == B.EUNSUPPORTED
+    # stage timing needs all primes at once
+    with pytest.raises(pdm.PolydetError) as e:
+        pdm.plan(12, (3, 3, 3), host_coeffs=arr, flags=H | pdm.STAGE_TIMING,
+                 max_workspace=full["workspace_bytes"] // 2)
+    assert e.value.status == B.EINVAL
+    # integer matrices are never split
+    a = np.array([[3, 1], [2, 2 ** 40]], dtype=np.int64)
+    info = pdm.plan(2, (), host_coeffs=a, flags=H).info
+    with pytest.raises(pdm.PolydetError):
+        pdm.plan(2, (), host_coeffs=a, flags=H, max_workspace=info["workspace_bytes"] - 256)
+
+
+def test_prime_range_and_reconstruct_reject_bad_arguments():
+    lib = pdm.load_library()
+    pl = pdm.plan(4, (2, 2), coeff_bits=4, flags=pdm.HOST_ONLY)
+    dummy = ctypes.c_void_p(256)
+    ws = pl.info["workspace_bytes"]
+    # a host-only plan, a bad range, a batch plan
+    assert lib.polydet_solve_primes(pl.handle, dummy, 0, 1, dummy, ws, None) == B.EINVAL
+    assert lib.polydet_reconstruct(pl.handle, dummy, ws, dummy, None) == B.EINVAL
+    assert lib.polydet_solve_primes(None, dummy, 0, 1, dummy, ws, None) == B.EINVAL
+    bp = pdm.plan_batch(W.config4(count=4), flags=pdm.HOST_ONLY)
+    assert lib.polydet_solve_primes(bp.handle, dummy, 0, 1, dummy, 1 << 40, None) == B.EINVAL
