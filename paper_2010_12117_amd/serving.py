@@ -10,16 +10,23 @@ and the result limbs come out.
 
 Admission is first come, first served with reservation: when the oldest waiting job does
 not fit, its memory is reserved, and younger jobs may start only if they fit beside that
-reservation. Large jobs therefore cannot starve while small ones keep flowing.
+reservation. Large jobs therefore cannot starve while small ones keep flowing. A job whose
+one-shot footprint exceeds the whole budget runs on a capped plan (polydet_plan_capped:
+primes in groups, same result) when one prime's footprint fits.
 
-The solve itself is `polydet_solve` (binding.py); this module only schedules it.
+With `prime_chunk`, a job runs as a sequence of prime ranges (polydet_solve_primes), one range
+in flight at a time, then the reconstruction (polydet_reconstruct). Between ranges the server
+can stop it: `cancel` ends a waiting job at once and a running one at its next range boundary,
+and its future raises CancelledError.
+
+The solve itself is the library's (binding.py); this module only schedules it.
 """
 from __future__ import annotations
 
 import collections
 import threading
 import time
-from concurrent.futures import Future
+from concurrent.futures import CancelledError, Future
 from dataclasses import dataclass, field
 from typing import Deque, List, Optional
 
@@ -63,21 +70,27 @@ class _Job:
     buffers: tuple = ()
     host_out: object = None
     done_event: object = None
+    next_prime: int = 0    # chunked jobs: first prime not yet enqueued
+    final: bool = False    # the reconstruction and the copy-out are enqueued
+    cancelled: bool = False
 
 
 class Server:
     """Admits determinant jobs by device memory footprint and runs them concurrently.
 
     memory_budget: device bytes the server may hold for jobs at once.
-    slots: jobs in flight at once (one stream each)."""
+    slots: jobs in flight at once (one stream each).
+    prime_chunk: primes per enqueued range (None: the whole solve at once)."""
 
     def __init__(self, memory_budget: int = 64 << 30, slots: int = 4, device: str = "cuda:0",
-                 flags: int = 0):
+                 flags: int = 0, prime_chunk=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.budget = int(memory_budget)
         self.flags = flags
+        self.prime_chunk = prime_chunk
+        self.jobs_by_future = {}
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
         self.free_streams = list(range(slots))
         self.queue: Deque[_Job] = collections.deque()
@@ -98,15 +111,43 @@ class Server:
         info = pl.info
         footprint = int(info["in_bytes"] + info["workspace_bytes"] + info["out_bytes"])
         if footprint > self.budget:
-            raise ValueError(f"job needs {footprint} device bytes, above the server budget")
+            # primes in groups: the workspace shrinks to what the budget leaves
+            cap = self.budget - info["in_bytes"] - info["out_bytes"]
+            too_big = ValueError(f"job needs {footprint} device bytes one-shot and does not fit "
+                                 "the server budget even one prime at a time")
+            if cap <= 0:
+                raise too_big
+            try:
+                pl = B.plan(n, deg, host_coeffs=coeffs, flags=self.flags, max_workspace=cap)
+            except B.PolydetError:
+                raise too_big from None
+            info = pl.info
+            footprint = int(info["in_bytes"] + info["workspace_bytes"] + info["out_bytes"])
         fut: Future = Future()
         job = _Job(coeffs, pl, footprint, fut, time.perf_counter())
         with self.lock:
             if self.closed:
                 raise RuntimeError("server is closed")
             self.queue.append(job)
+            self.jobs_by_future[id(fut)] = job
             self.lock.notify()
         return fut
+
+    def cancel(self, fut: Future) -> bool:
+        """Stop a job: a waiting one now, a running chunked one at its next range boundary.
+        Returns False when the job has already finished."""
+        with self.lock:
+            job = self.jobs_by_future.get(id(fut))
+            if job is None or fut.done():
+                return False
+            if job in self.queue:
+                self.queue.remove(job)
+                del self.jobs_by_future[id(fut)]
+                fut.set_exception(CancelledError())
+            else:
+                job.cancelled = True
+            self.lock.notify()
+            return True
 
     def close(self, wait: bool = True):
         with self.lock:
@@ -150,23 +191,70 @@ class Server:
             d_out = torch.empty((info["ncoeff"], info["limbs"]), dtype=torch.int32,
                                 device=self.device)
             ws = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device=self.device)
-            B.solve_device(job.plan, d_in, d_out, ws, stream=stream)
             job.host_out = torch.empty(d_out.shape, dtype=torch.int32, pin_memory=True)
-            job.host_out.copy_(d_out, non_blocking=True)
-            job.done_event = torch.cuda.Event()
-            job.done_event.record(stream)
         job.buffers = (host_in, d_in, d_out, ws)
+        if self.prime_chunk:
+            self._enqueue_range(job)
+        else:
+            with torch.cuda.stream(stream):
+                B.solve_device(job.plan, d_in, d_out, ws, stream=stream)
+            self._enqueue_copy_out(job)
         self.running.append(job)
+
+    def _record(self, job: _Job):
+        job.done_event = self.torch.cuda.Event()
+        job.done_event.record(self.streams[job.stream])
+
+    def _enqueue_range(self, job: _Job):
+        """The next range of primes of a chunked job."""
+        _, d_in, _, ws = job.buffers
+        pn = job.plan.info["pn"]
+        b, e = job.next_prime, min(pn, job.next_prime + int(self.prime_chunk))
+        B.solve_primes_device(job.plan, d_in, b, e, ws, stream=self.streams[job.stream])
+        job.next_prime = e
+        self._record(job)
+
+    def _enqueue_copy_out(self, job: _Job):
+        """(chunked jobs: the reconstruction, then) the copy of the limbs to pinned memory."""
+        stream = self.streams[job.stream]
+        _, _, d_out, ws = job.buffers
+        if self.prime_chunk:
+            B.reconstruct_device(job.plan, ws, d_out, stream=stream)
+        with self.torch.cuda.stream(stream):
+            job.host_out.copy_(d_out, non_blocking=True)
+        job.final = True
+        self._record(job)
+
+    def _release(self, job: _Job):
+        # the buffers were used on the job's stream only, and that stream is done
+        job.buffers = ()
+        self.in_use -= job.footprint
+        self.free_streams.append(job.stream)
+        self.jobs_by_future.pop(id(job.future), None)
+
+    def _advance(self, job: _Job) -> bool:
+        """A running job's last enqueued work is done: enqueue what comes next. Returns True
+        when the job has left the running set."""
+        if job.cancelled:
+            self._release(job)
+            job.host_out = None
+            job.future.set_exception(CancelledError())
+            return True
+        if job.final:
+            self._finish(job)
+            return True
+        if job.next_prime < job.plan.info["pn"]:
+            self._enqueue_range(job)
+        else:
+            self._enqueue_copy_out(job)
+        return False
 
     def _finish(self, job: _Job):
         now = time.perf_counter()
         info = job.plan.info
         res = Result(job.host_out.numpy().copy(), info, job.submitted, job.started, now)
-        # the buffers were used on the job's stream only, and that stream is done
-        job.buffers = ()
         job.host_out = None
-        self.in_use -= job.footprint
-        self.free_streams.append(job.stream)
+        self._release(job)
         self.latencies.append(res.latency)
         self.completed += 1
         job.future.set_result(res)
@@ -189,12 +277,14 @@ class Server:
             with self.lock:
                 done = [j for j in self.running if j.done_event.query()]
                 for j in done:
-                    self.running.remove(j)
-                for j in done:
                     try:
-                        self._finish(j)
+                        left = self._advance(j)
                     except Exception as e:  # pragma: no cover - surfaced to the client
+                        left = True
+                        self._release(j)
                         j.future.set_exception(e)
+                    if left:
+                        self.running.remove(j)
                 try:
                     self._admit()
                 except Exception as e:  # pragma: no cover

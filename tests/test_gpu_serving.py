@@ -75,3 +75,45 @@ def test_out_of_order_completion():
     assert order[0] != 0  # some small job finished before the first one
     for a, r in zip(jobs, results):
         assert np.array_equal(r.limbs, alone(a))
+
+
+def test_chunked_jobs_equal_alone():
+    jobs = small_jobs(11, 10) + [W.config2()]
+    srv = S.Server(memory_budget=8 << 30, slots=3, prime_chunk=2)
+    futs = [srv.submit(a) for a in jobs]
+    results = [f.result(timeout=120) for f in futs]
+    srv.close()
+    for a, r in zip(jobs, results):
+        assert np.array_equal(r.limbs, alone(a))
+
+
+def test_cancel_waiting_and_running_jobs():
+    from concurrent.futures import CancelledError
+    big = W.config2()
+    smalls = small_jobs(12, 4)
+    srv = S.Server(memory_budget=8 << 30, slots=1, prime_chunk=1)
+    f_big = srv.submit(big)
+    f_small = [srv.submit(a) for a in smalls]
+    # the last small job is still waiting behind the others on the single slot
+    assert srv.cancel(f_small[-1])
+    with pytest.raises(CancelledError):
+        f_small[-1].result(timeout=5)
+    assert srv.cancel(f_big)  # running (or about to start): stops at a prime boundary
+    with pytest.raises(CancelledError):
+        f_big.result(timeout=60)
+    for a, f in zip(smalls[:-1], f_small[:-1]):
+        assert np.array_equal(f.result(timeout=60).limbs, alone(a))
+    assert not srv.cancel(f_small[0])  # already finished
+    srv.close()
+    assert srv.in_use == 0
+
+
+def test_job_above_budget_runs_on_a_capped_plan():
+    a = W.config2()
+    info = pdm.plan(12, (3, 3, 3), host_coeffs=a, flags=pdm.HOST_ONLY).info
+    full = info["in_bytes"] + info["workspace_bytes"] + info["out_bytes"]
+    srv = S.Server(memory_budget=full // 2, slots=2)
+    r = srv.submit(a).result(timeout=120)
+    srv.close()
+    assert r.info["prime_group"] < r.info["pn"]
+    assert np.array_equal(r.limbs, alone(a))
