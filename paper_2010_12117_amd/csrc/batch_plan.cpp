@@ -168,12 +168,12 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         e.tw_stride = P.tw_stride;
         e.m = P.m[v];
         e.Nv = P.N[v];
-        e.JC = expand_outputs_per_thread(P.N[v], inner);
+        e.JC = expand_outputs_per_thread(P.N[v], inner, P.m[v]);
         e.tw = P.d_tw + P.tw_off[v];
         e.pc = P.d_pc;
         e.zero = P.d_zero;
         d.push_back(e);
-        vb += (e.B * outer * (e.Nv / e.JC) * inner + 255) / 256;
+        vb += (e.B * outer * (expand_jrange(e.Nv, e.m) / e.JC) * inner + 255) / 256;
       }
       if (d.empty()) continue;
       BLaunch L{};

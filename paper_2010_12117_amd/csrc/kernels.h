@@ -14,7 +14,7 @@ constexpr int kTileElems = 8192;  // interpolation tile: at most 32 KB of LDS pe
 bool det_config_supported(int n, int lanes);
 
 // Launch shapes shared by the single and the batched paths.
-int expand_outputs_per_thread(int Nv, int64_t inner);
+int expand_outputs_per_thread(int Nv, int64_t inner, int m);
 int intt_lines_per_block(int64_t lines, int Nv, int pn);
 int64_t finalize_threads(int64_t G, int pn);  // threads of the det = num / den launch
 

@@ -83,30 +83,42 @@ __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
 //   out [B][outer][Nv][inner]  out[j] = sum_e in[e] w_v^{e j}
 // the values at the Nv-th roots of unity (the DFT over Z/pZ of Section 2, restricted to the
 // m nonzero leading coefficients of the zero-padded line). b = prime * nent + entry.
-// A thread computes JC consecutive outputs j of one line; consecutive lanes take
-// consecutive q (coalesced when inner >= 64) and, for small inner, consecutive j-chunks, so
-// that short lines still spread over many lanes with contiguous stores. M >= m is the
-// register bound on the coefficients; terms e >= m are skipped (a uniform test).
+// With m >= 2 the outputs come in pairs: since w^{Nv/2} = -1, out[j] = E + O and
+// out[j + Nv/2] = E - O, with E the even terms and O the odd terms at j, so a thread takes
+// j in [0, Nv/2) and half the products. A thread computes JC consecutive j of one line;
+// consecutive lanes take consecutive q (coalesced when inner >= 64) and, for small inner,
+// consecutive j-chunks. M >= m bounds the coefficients held in registers; terms e >= m are
+// skipped (a uniform test). Lines of structurally zero entries are written as zeros only when
+// the output is read without the zero flags (write_zero: the full evaluation tensor).
 // ------------------------------------------------------------------------------------
 template <int M>
 __device__ __forceinline__ void expand_body(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t idx, int64_t B,
     int64_t outer, int m, int Nv, int JC, int64_t inner, int64_t nent,
     const uint32_t* __restrict__ tw, int64_t tw_stride, const PrimeConst* __restrict__ pcs,
-    const uint8_t* __restrict__ zero) {
-  const int nJB = Nv / JC;
+    const uint8_t* __restrict__ zero, bool write_zero) {
+  const bool paired = expand_paired(Nv, m);
+  const int NJ = paired ? Nv / 2 : Nv;
+  const int nJB = NJ / JC;
   if (idx >= B * outer * nJB * inner) return;
-  const int64_t q = idx % inner;
-  const int64_t r = idx / inner;
-  const int jb = (int)(r % nJB);
-  const int64_t bo = r / nJB;
+  // inner and nJB are powers of two
+  const int li = __builtin_ctzll((unsigned long long)inner);
+  const int64_t q = idx & (inner - 1);
+  const int64_t r = idx >> li;
+  const int jb = (int)(r & (nJB - 1));
+  const int64_t bo = r >> __builtin_ctz((unsigned)nJB);
   const int64_t b = bo / outer;
   const int prime = (int)(b / nent);
   const int64_t entry = b - (int64_t)prime * nent;
   uint32_t* dst = out + bo * Nv * inner + q;
   const int j0 = jb * JC;
   if (zero && zero[entry]) {
-    for (int j = j0; j < j0 + JC; ++j) dst[(int64_t)j * inner] = 0u;
+    if (write_zero) {
+      for (int j = j0; j < j0 + JC; ++j) {
+        dst[(int64_t)j * inner] = 0u;
+        if (paired) dst[(int64_t)(j + NJ) * inner] = 0u;
+      }
+    }
     return;
   }
   const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv;
@@ -116,20 +128,34 @@ __device__ __forceinline__ void expand_body(
 #pragma unroll
   for (int e = 0; e < M; ++e) x[e] = e < m ? src[(int64_t)e * inner] : 0u;
   const int mask = Nv - 1;
-  for (int j = j0; j < j0 + JC; ++j) {
-    uint32_t acc = x[0];
+  if (paired) {
+    for (int j = j0; j < j0 + JC; ++j) {
+      // E = x0 + (x2 w^2j + x4 w^4j) + ..., O = (x1 w^j + x3 w^3j) + ..., two per reduction
+      uint32_t E = x[0], O = 0u;
 #pragma unroll
-    for (int e = 1; e < M; e += 2) {
-      if (e < m) {
-        if (e + 1 < M) {
-          acc = addm(acc,
-                     mm2(x[e], w[(e * j) & mask], x[e + 1], w[((e + 1) * j) & mask], p, pinv), p);
-        } else {
-          acc = addm(acc, mm(x[e], w[(e * j) & mask], p, pinv), p);
+      for (int e = 2; e < M; e += 4) {
+        if (e < m) {
+          if (e + 2 < M && e + 2 < m)
+            E = addm(E, mm2(x[e], w[(e * j) & mask], x[e + 2], w[((e + 2) * j) & mask], p, pinv), p);
+          else
+            E = addm(E, mm(x[e], w[(e * j) & mask], p, pinv), p);
         }
       }
+#pragma unroll
+      for (int e = 1; e < M; e += 4) {
+        if (e < m) {
+          if (e + 2 < M && e + 2 < m)
+            O = addm(O, mm2(x[e], w[(e * j) & mask], x[e + 2], w[((e + 2) * j) & mask], p, pinv), p);
+          else
+            O = addm(O, mm(x[e], w[(e * j) & mask], p, pinv), p);
+        }
+      }
+      dst[(int64_t)j * inner] = addm(E, O, p);
+      dst[(int64_t)(j + NJ) * inner] = subm(E, O, p);
     }
-    dst[(int64_t)j * inner] = acc;
+  } else {
+    // m == 1: the line is its constant term at every point
+    for (int j = j0; j < j0 + JC; ++j) dst[(int64_t)j * inner] = x[0];
   }
 }
 
@@ -137,9 +163,11 @@ template <int M>
 __global__ __launch_bounds__(kBlock) void expand_kernel(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t B, int64_t outer,
     int m, int Nv, int JC, int64_t inner, int64_t nent, const uint32_t* __restrict__ tw,
-    int64_t tw_stride, const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
+    int64_t tw_stride, const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
+    bool write_zero) {
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  expand_body<M>(in, out, idx, B, outer, m, Nv, JC, inner, nent, tw, tw_stride, pcs, zero);
+  expand_body<M>(in, out, idx, B, outer, m, Nv, JC, inner, nent, tw, tw_stride, pcs, zero,
+                 write_zero);
 }
 
 __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __restrict__ desc,
@@ -150,15 +178,16 @@ __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __r
     const int64_t idx = (vb - d.block0) * kBlock + threadIdx.x;
     expand_body<kBatchMaxM>((const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), idx,
                             d.B, d.outer, d.m, d.Nv, d.JC, d.inner, d.nent, d.tw, d.tw_stride,
-                            d.pc, d.zero);
+                            d.pc, d.zero, false);
   }
 }
 
 // ------------------------------------------------------------------------------------
-// S3 (end): det = num / den at every point. A thread takes kFinalPoints consecutive points
-// of one prime and inverts their denominators together (Montgomery's simultaneous
-// inversion: prefix products, one Fermat inverse, then back-substitution), which costs one
-// exponentiation per kFinalPoints points instead of one per point. Every den is nonzero.
+// S3 (end): det = num / den at every point. A thread takes kFinalPoints points of one prime,
+// chunks apart (so that a wave's loads and stores are contiguous), and inverts their
+// denominators together (Montgomery's simultaneous inversion: prefix products, one Fermat
+// inverse, then back-substitution), which costs one exponentiation per kFinalPoints points
+// instead of one per point. Every den is nonzero.
 // ------------------------------------------------------------------------------------
 constexpr int kFinalPoints = 8;
 
@@ -167,15 +196,15 @@ __device__ __forceinline__ void finalize_body(uint32_t* __restrict__ detv,
                                               int64_t G, const PrimeConst* __restrict__ pcs) {
   const int64_t chunks = (G + kFinalPoints - 1) / kFinalPoints;
   const int prime = (int)(t / chunks);
-  const int64_t i0 = (t - (int64_t)prime * chunks) * kFinalPoints;
+  const int64_t c = t - (int64_t)prime * chunks;  // points c, c + chunks, c + 2 chunks, ...
   const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
-  uint32_t* num = detv + (int64_t)prime * G + i0;
-  const uint32_t* den = denv + (int64_t)prime * G + i0;
+  uint32_t* num = detv + (int64_t)prime * G + c;
+  const uint32_t* den = denv + (int64_t)prime * G + c;
   uint32_t d[kFinalPoints], pre[kFinalPoints];
   uint32_t acc = one;
 #pragma unroll
   for (int i = 0; i < kFinalPoints; ++i) {
-    d[i] = (i0 + i < G) ? den[i] : one;
+    d[i] = (c + i * chunks < G) ? den[i * chunks] : one;
     pre[i] = acc;  // product of the denominators before i
     acc = mm(acc, d[i], p, pinv);
   }
@@ -184,7 +213,7 @@ __device__ __forceinline__ void finalize_body(uint32_t* __restrict__ detv,
   for (int i = kFinalPoints - 1; i >= 0; --i) {
     const uint32_t di = mm(inv, pre[i], p, pinv);  // 1 / d[i]
     inv = mm(inv, d[i], p, pinv);                   // 1 / (d[0] .. d[i-1])
-    if (i0 + i < G) num[i] = mm(num[i], di, p, pinv);
+    if (c + i * chunks < G) num[i * chunks] = mm(num[i * chunks], di, p, pinv);
   }
 }
 
@@ -230,14 +259,18 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
   uint32_t* dst = out + (int64_t)prime * outer * Dv1 * inner;
   const int nW = (int)((lines - line0) < W ? (lines - line0) : W);
   const int total = Nv * W;
+  // W, Nv and inner are powers of two: the index arithmetic below is shifts and masks
+  const int lW = __builtin_ctz((unsigned)W);
+  const int lI = __builtin_ctzll((unsigned long long)inner);
+  const int64_t imask = inner - 1;
   // load: element j of local line l goes to tile[brev(j) * W + l]
   for (int idx = threadIdx.x; idx < total; idx += kBlock) {
     int j, l;
-    if (inner >= W) { j = idx / W; l = idx % W; } else { l = idx / Nv; j = idx % Nv; }
+    if (inner >= W) { j = idx >> lW; l = idx & (W - 1); } else { l = idx >> logN; j = idx & (Nv - 1); }
     uint32_t v = 0u;
     if (l < nW) {
       const int64_t line = line0 + l;
-      const int64_t o = line / inner, q = line % inner;
+      const int64_t o = line >> lI, q = line & imask;
       v = src[(o * Nv + j) * inner + q];
     }
     const int rj = logN ? (int)(__brev((unsigned)j) >> (32 - logN)) : 0;
@@ -248,9 +281,9 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
     const int half = 1 << (s - 1);
     const int stride = Nv >> s;  // twiddle index step: w^{pos * N / 2^s}
     for (int bi = threadIdx.x; bi < (Nv / 2) * W; bi += kBlock) {
-      const int l = bi % W;
-      const int b = bi / W;
-      const int grp = b / half, pos = b % half;
+      const int l = bi & (W - 1);
+      const int b = bi >> lW;
+      const int grp = b >> (s - 1), pos = b & (half - 1);
       const int i0 = grp * 2 * half + pos, i1 = i0 + half;
       const uint32_t u = tile[i0 * W + l];
       const uint32_t v = mm(tile[i1 * W + l], w[pos * stride], p, pinv);
@@ -262,10 +295,10 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
   const int otot = Dv1 * W;
   for (int idx = threadIdx.x; idx < otot; idx += kBlock) {
     int e, l;
-    if (inner >= W) { e = idx / W; l = idx % W; } else { l = idx / Dv1; e = idx % Dv1; }
+    if (inner >= W) { e = idx >> lW; l = idx & (W - 1); } else { l = idx / Dv1; e = idx - l * Dv1; }
     if (l < nW) {
       const int64_t line = line0 + l;
-      const int64_t o = line / inner, q = line % inner;
+      const int64_t o = line >> lI, q = line & imask;
       dst[(o * Dv1 + e) * inner + q] = tile[e * W + l];
     }
   }
@@ -425,11 +458,13 @@ template <int M>
 hipError_t launch_expand_m(const MatPlan& P, const uint32_t* in, uint32_t* out, int64_t outer,
                            int v, int64_t inner, hipStream_t st) {
   const int64_t B = (int64_t)P.pn * P.nent;
-  const int JC = expand_outputs_per_thread(P.N[v], inner);
-  const int64_t work = B * outer * (P.N[v] / JC) * inner;
+  const int JC = expand_outputs_per_thread(P.N[v], inner, P.m[v]);
+  const int64_t work = B * outer * (expand_jrange(P.N[v], P.m[v]) / JC) * inner;
+  // the full evaluation tensor (last pass of the unfused path) is read without zero flags
+  const bool write_zero = v == 0;
   hipLaunchKernelGGL(expand_kernel<M>, dim3(blocks_for(work)), dim3(kBlock), 0, st, in, out, B,
                      outer, P.m[v], P.N[v], JC, inner, P.nent, P.d_tw + P.tw_off[v], P.tw_stride,
-                     P.d_pc, P.d_zero);
+                     P.d_pc, P.d_zero, write_zero);
   return hipGetLastError();
 }
 
@@ -569,11 +604,12 @@ bool det_config_supported(int n, int lanes) {
   }
 }
 
-int expand_outputs_per_thread(int Nv, int64_t inner) {
+int expand_outputs_per_thread(int Nv, int64_t inner, int m) {
   // enough threads per line that a wave covers at least 64 consecutive outputs
+  const int NJ = expand_jrange(Nv, m);
   int nJB = 1;
-  while (nJB < Nv && nJB * inner < 64) nJB <<= 1;
-  return Nv / nJB;
+  while (nJB < NJ && nJB * inner < 64) nJB <<= 1;
+  return NJ / nJB;
 }
 
 int intt_lines_per_block(int64_t lines, int Nv, int pn) {

@@ -34,6 +34,11 @@ PD_HD int fused_slots(int block, int lanes, int m0) {
   return (fused_paired(m0) ? block / 2 : block) / lanes;
 }
 
+// Evaluation passes (expand kernel) compute the outputs j and j + Nv/2 of a line together
+// when the line has m >= 2 coefficients; their threads cover j in [0, expand_jrange).
+PD_HD bool expand_paired(int Nv, int m) { return m >= 2 && Nv >= 2; }
+PD_HD int expand_jrange(int Nv, int m) { return expand_paired(Nv, m) ? Nv / 2 : Nv; }
+
 // LDS words of a fused elimination block's tile: m0 coefficient rows of Q points, each a
 // matrix whose n rows are padded to a multiple of the lanes per matrix, with an odd stride.
 PD_HD size_t fused_tile_words(int n, int lanes, int m0, int Q) {
