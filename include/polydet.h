@@ -20,8 +20,9 @@
  * Degree bound: D[v] = n * deg[v], an upper bound on the determinant's degree in x_v.
  * Grid: N[v] = next power of two >= D[v] + 1 (the paper rounds degrees up to powers of two,
  *   Section 2; interpolation needs D[v] + 1 distinct nodes, Theorem 1), G = prod N[v].
- * Primes: p in (2^30, 2^31) with p = 1 mod 2^16, in descending order ("9-digit" primes
- *   of the form c * 2^q + 1, Section 2). The count pn is the least with
+ * Primes: p in (2^29, 2^30) with p = 1 mod 2^16, in descending order ("9-digit" primes
+ *   of the form c * 2^q + 1, Section 2; below 2^30 the elimination may leave its entries
+ *   unreduced in [0, 2p) between steps). The count pn is the least with
  *   (p_0 ... p_{pn-1})^2 > 4 B^2, where B^2 = min(prod_i sum_j |a_ij|_1^2,
  *   prod_j sum_i |a_ij|_1^2) bounds the squared coefficients of det M (Hadamard's
  *   inequality on 1-norms; the paper says only that the bound is easily computed).

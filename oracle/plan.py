@@ -16,7 +16,8 @@ Readings taken where the paper is silent:
   N_v = next_pow2(D_v + 1) with D_v a bound on the determinant's degree in x_v;
 * coefficients are recovered in the symmetric range, so the primes' product M must satisfy
   M > 2B, checked exactly as M^2 > 4 B^2;
-* the primes are those in (2^30, 2^31) with p = 1 mod 2^16, in descending order.
+* the primes are those in (2^29, 2^30) with p = 1 mod 2^16, in descending order: the
+  "9-digit" primes c * 2^q + 1 of Section 2, about 10^9.
 """
 from __future__ import annotations
 
@@ -26,8 +27,8 @@ import numpy as np
 
 from . import poly as P
 
-PRIME_LO = 1 << 30
-PRIME_HI = 1 << 31
+PRIME_LO = 1 << 29
+PRIME_HI = 1 << 30
 PRIME_TWO_ADICITY = 16
 
 
@@ -122,7 +123,7 @@ def is_prime(m: int) -> bool:
 
 
 def ntt_primes(count: int) -> List[int]:
-    """The first `count` primes p in (2^30, 2^31) with p = 1 mod 2^16, descending."""
+    """The first `count` primes p in (2^29, 2^30) with p = 1 mod 2^16, descending."""
     out = []
     step = 1 << PRIME_TWO_ADICITY
     c = (PRIME_HI - 1) // step

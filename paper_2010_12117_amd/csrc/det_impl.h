@@ -102,7 +102,10 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
 // pi_k^{n-k-2} (the representative of 1 for a singular matrix, so that den is never 0).
 // The division is left to finalize_kernel, which inverts the denominators of many points
 // with one exponentiation. Every lane of the group returns the pair; all lanes of the wave
-// must call this together (lane shuffles).
+// must call this together (lane broadcasts).
+// Entries may come in unreduced, in [0, 2p), and stay so: each step reduces only its pivot
+// column (for the zero test, the exchange and the multipliers), and the updates use
+// mm2_lazy, whose sum of products stays below 4 p^2 < p R with p < 2^30.
 struct DetFrac {
   uint32_t num, den;
 };
@@ -117,6 +120,10 @@ __device__ __forceinline__ DetFrac eliminate(uint32_t (&a)[(N + GL - 1) / GL][N]
 #pragma unroll
   for (int k = 0; k < N - 1; ++k) {
     const int s = k / GL, o = k % GL;
+    // slot s holds column k in lane o of the group: reduce it (the other lanes' columns in
+    // the slot come along; a reduced value is a valid unreduced one)
+#pragma unroll
+    for (int i = k; i < N; ++i) a[s][i] = fold(a[s][i], p);
     const uint32_t zero_piv = bcast<GL>(a[s][k] == 0u ? 1u : 0u, o);
     if (__any(zero_piv != 0u)) {
       int r = N;
@@ -142,7 +149,7 @@ __device__ __forceinline__ DetFrac eliminate(uint32_t (&a)[(N + GL - 1) / GL][N]
     for (int i = k + 1; i < N; ++i) {
       const uint32_t mi = p - bcast<GL>(a[s][i], o);  // -A[i][k]; p stands for 0
 #pragma unroll
-      for (int c = s; c < C; ++c) a[c][i] = mm2(piv, a[c][i], mi, a[c][k], p, pinv);
+      for (int c = s; c < C; ++c) a[c][i] = mm2_lazy(piv, a[c][i], mi, a[c][k], p, pinv);
     }
     if (k <= N - 3) {
       e = mm(e, piv, p, pinv);
@@ -150,7 +157,7 @@ __device__ __forceinline__ DetFrac eliminate(uint32_t (&a)[(N + GL - 1) / GL][N]
     }
   }
   constexpr int sl = (N - 1) / GL, ol = (N - 1) % GL;
-  const uint32_t last = bcast<GL>(a[sl][N - 1], ol);
+  const uint32_t last = fold(bcast<GL>(a[sl][N - 1], ol), p);
   dead = dead || (last == 0u);
   DetFrac f;
   f.num = dead ? 0u : (flip ? negm(last, p) : last);
@@ -343,8 +350,12 @@ __device__ __forceinline__ void det_fused_body(
             a[c][i] = 0u;
           } else {
             const uint32_t v = mm2(ra[off], wa, rb[off], wb, p, pinv);
+            // every lane now holds E (the lower lane's v) and O (the upper lane's v). Keep
+            // E + O (lower lane) or E + (p - O) (upper lane), as E + (O ^ sm) + sc: with
+            // sm = -1 and sc = p + 1, (O ^ sm) + sc = p - O. Both lie below 2p and are left
+            // unreduced for the elimination.
             const auto eo = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-            a[c][i] = fold(eo[0] + (eo[1] ^ sm) + sc, p);
+            a[c][i] = eo[0] + (eo[1] ^ sm) + sc;
           }
           // without a branch per entry (GL > 1) the scheduler would run every product first
           // and keep all of them live until their exchanges: bound its window

@@ -1,12 +1,15 @@
-// Modular arithmetic over Z/pZ for word-size primes p in (2^30, 2^31).
+// Modular arithmetic over Z/pZ for word-size primes p in (2^29, 2^30).
 //
 // Values are kept in Montgomery form x~ = x * R mod p with R = 2^32 (Montgomery 1985):
 // the product of two representatives reduced by REDC is the representative of the product,
 // so every stage (evaluation, elimination, interpolation) runs on representatives and only
 // the reconstruction converts back. REDC(t) = (t + m p) / R with m = t * (-p^{-1}) mod R;
 // for t < p R it returns a value below 2p, and one conditional subtraction finishes it.
-// With p < 2^31 a sum of two products of reduced values stays below 2 p^2 < p R, which
-// lets the elimination update fold two products into one reduction.
+// A sum of two products of reduced values stays below 2 p^2 < p R, which lets the
+// elimination update fold two products into one reduction. Since p < 2^30, the sum may even
+// have one factor of each product below 2p (then t < 4 p^2 < p R): the elimination keeps its
+// entries unreduced in [0, 2p) and skips the conditional subtraction of most updates
+// (mm2_lazy).
 //
 // On gfx950 v_mad_u64_u32 and v_mul_lo_u32 issue at the fp64-FMA rate and plain 32-bit
 // ALU ops at twice that, so one REDC costs one mul_lo, one mad_u64 and two plain ops.
@@ -43,6 +46,17 @@ PD_HD uint32_t mm(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
 // (a b + c d) / R with every operand below p: one reduction for two products.
 PD_HD uint32_t mm2(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t p, uint32_t pinv) {
   return redc((uint64_t)a * b + (uint64_t)c * d, p, pinv);
+}
+
+// (a b + c d) / R in [0, 2p) with a, c <= p and b, d < 2p (t < 4 p^2 < p R for p < 2^30).
+PD_HD uint32_t mm2_lazy(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t p,
+                        uint32_t pinv) {
+  const uint64_t t = (uint64_t)a * b + (uint64_t)c * d;
+  const uint32_t m = (uint32_t)t * pinv;
+  // The mask changes nothing (the value is below 2p < 2^31) but keeps it a 32-bit value:
+  // without it the compiler widens the next product's operand to the 64-bit shifted sum
+  // (its high half known zero) and holds two registers per entry.
+  return (uint32_t)((t + (uint64_t)m * p) >> 32) & 0x7FFFFFFFu;
 }
 
 PD_HD uint32_t addm(uint32_t a, uint32_t b, uint32_t p) { return fold(a + b, p); }

@@ -84,9 +84,9 @@ const std::vector<uint32_t>& prime_table() {
   static const std::vector<uint32_t> table = [] {
     std::vector<uint32_t> t;
     const uint64_t step = 1ull << 16;
-    for (uint64_t c = ((1ull << 31) - 1) / step; c * step + 1 > (1ull << 30); --c) {
+    for (uint64_t c = ((1ull << 30) - 1) / step; c * step + 1 > (1ull << 29); --c) {
       const uint64_t p = c * step + 1;
-      if (p < (1ull << 31) && is_prime_u32((uint32_t)p)) t.push_back((uint32_t)p);
+      if (p < (1ull << 30) && is_prime_u32((uint32_t)p)) t.push_back((uint32_t)p);
     }
     return t;
   }();

@@ -56,7 +56,7 @@ struct Tuning {
 void set_tuning(const Tuning& t);
 Tuning get_tuning();
 
-// The descending table of primes p in (2^30, 2^31) with p = 1 mod 2^16.
+// The descending table of primes p in (2^29, 2^30) with p = 1 mod 2^16 (784 of them).
 const std::vector<uint32_t>& prime_table();
 uint32_t primitive_root(uint32_t p);
 uint32_t powmod(uint32_t b, uint64_t e, uint32_t p);

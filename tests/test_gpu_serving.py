@@ -62,11 +62,12 @@ def test_oversized_job_is_rejected():
 
 def test_out_of_order_completion():
     # a large job first, then small ones on the other slots: the small ones finish first and
-    # leave the running list from the middle
+    # leave the running list from the middle. One prime per enqueued range keeps the large
+    # job in flight over many turns of the server loop, whatever the GPU's speed.
     rng = np.random.default_rng(77)
-    big = W.random_matrix(rng, 24, (3, 3, 3), -1000, 1000)  # about 0.1 s of GPU work
+    big = W.random_matrix(rng, 24, (3, 3, 3), -1000, 1000)
     jobs = [big] + small_jobs(5, 16)
-    srv = S.Server(memory_budget=8 << 30, slots=4)
+    srv = S.Server(memory_budget=8 << 30, slots=4, prime_chunk=1)
     futs = [srv.submit(a) for a in jobs]
     results = [f.result(timeout=120) for f in futs]
     srv.close()

@@ -278,7 +278,7 @@ def test_ntt_primes_against_sympy():
     for p in ps:
         assert sympy.isprime(p)
         assert (p - 1) % (1 << 16) == 0
-        assert (1 << 30) < p < (1 << 31)
+        assert (1 << 29) < p < (1 << 30)
     # no prime of that form is skipped between the first and the last
     lo, hi = ps[-1], ps[0]
     step = 1 << 16
@@ -288,12 +288,13 @@ def test_ntt_primes_against_sympy():
 
 
 def test_prime_supply_count():
-    # how many 31-bit primes of the form c * 2^16 + 1 exist in (2^30, 2^31)
+    # how many primes of the form c * 2^16 + 1 exist in (2^29, 2^30)
     step = 1 << 16
-    count = sum(1 for c in range((1 << 30) // step, (1 << 31) // step)
-                if c * step + 1 > (1 << 30) and sympy.isprime(c * step + 1))
-    assert count == 1530
-    assert PL.is_prime(2147352577) and not PL.is_prime(2147352577 - 2 * step)
+    count = sum(1 for c in range((1 << 29) // step, (1 << 30) // step)
+                if c * step + 1 > (1 << 29) and sympy.isprime(c * step + 1))
+    assert count == 784
+    assert PL.ntt_primes(1) == [1073479681]
+    assert PL.is_prime(1073479681) and not PL.is_prime(1073479681 + step)
 
 
 @pytest.mark.parametrize("N", [1, 2, 4, 16, 64, 1024, 65536])
