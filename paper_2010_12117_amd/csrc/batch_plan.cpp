@@ -290,7 +290,7 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         e.pc = P.d_pc;
         d.push_back(e);
         vb += e.tiles * P.pn;
-        lds = std::max(lds, (size_t)Nv * W * 4);
+        lds = std::max(lds, (size_t)(Nv * W + Nv / 2) * 4);  // tile and twiddles
       }
       if (d.empty()) continue;
       BLaunch L{};

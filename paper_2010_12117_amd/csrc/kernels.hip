@@ -90,8 +90,11 @@ __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
 // consecutive j-chunks. M >= m bounds the coefficients held in registers; terms e >= m are
 // skipped (a uniform test). Lines of structurally zero entries are written as zeros only when
 // the output is read without the zero flags (write_zero: the full evaluation tensor).
+// UJ (inner >= 64, a multiple of the wave): the 64 lanes of a wave share the line's position
+// r and so j, the prime and the entry; they are taken from the wave's first index, which lets
+// the twiddle, constant and zero-flag loads be scalar.
 // ------------------------------------------------------------------------------------
-template <int M>
+template <int M, bool UJ>
 __device__ __forceinline__ void expand_body(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t idx, int64_t B,
     int64_t outer, int m, int Nv, int JC, int64_t inner, int64_t nent,
@@ -104,7 +107,14 @@ __device__ __forceinline__ void expand_body(
   // inner and nJB are powers of two
   const int li = __builtin_ctzll((unsigned long long)inner);
   const int64_t q = idx & (inner - 1);
-  const int64_t r = idx >> li;
+  int64_t r;
+  if constexpr (UJ) {
+    const int64_t idx0 = (int64_t)blockIdx.x * kBlock +
+                         64 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    r = idx0 >> li;
+  } else {
+    r = idx >> li;
+  }
   const int jb = (int)(r & (nJB - 1));
   const int64_t bo = r >> __builtin_ctz((unsigned)nJB);
   const int64_t b = bo / outer;
@@ -159,15 +169,15 @@ __device__ __forceinline__ void expand_body(
   }
 }
 
-template <int M>
+template <int M, bool UJ>
 __global__ __launch_bounds__(kBlock) void expand_kernel(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t B, int64_t outer,
     int m, int Nv, int JC, int64_t inner, int64_t nent, const uint32_t* __restrict__ tw,
     int64_t tw_stride, const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
     bool write_zero) {
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  expand_body<M>(in, out, idx, B, outer, m, Nv, JC, inner, nent, tw, tw_stride, pcs, zero,
-                 write_zero);
+  expand_body<M, UJ>(in, out, idx, B, outer, m, Nv, JC, inner, nent, tw, tw_stride, pcs, zero,
+                     write_zero);
 }
 
 __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __restrict__ desc,
@@ -176,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __r
   for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
     const BExpand& d = desc[find_desc(desc, ndesc, vb)];
     const int64_t idx = (vb - d.block0) * kBlock + threadIdx.x;
-    expand_body<kBatchMaxM>((const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), idx,
+    expand_body<kBatchMaxM, false>((const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), idx,
                             d.B, d.outer, d.m, d.Nv, d.JC, d.inner, d.nent, d.tw, d.tw_stride,
                             d.pc, d.zero, false);
   }
@@ -240,8 +250,8 @@ __global__ __launch_bounds__(kBlock) void finalize_batch_kernel(const BFinal* __
 // ------------------------------------------------------------------------------------
 // S4: interpolation along one variable (inverse DFT: opposite sign in the exponent; the
 // 1/N factor is applied once in the reconstruction). A block loads a tile of W lines of
-// length Nv into LDS in bit-reversed order, runs log2 Nv radix-2 decimation-in-time stages
-// and writes the first D_v + 1 outputs of each line:
+// length Nv into LDS in bit-reversed order (with the Nv/2 twiddles it needs after it), runs
+// log2 Nv radix-2 decimation-in-time stages and writes the first D_v + 1 outputs of each line:
 //   in  [pn][outer][Nv][inner] -> out [pn][outer][Dv1][inner];  tile index = prime * tiles + t.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __restrict__ in,
@@ -263,6 +273,10 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
   const int lW = __builtin_ctz((unsigned)W);
   const int lI = __builtin_ctzll((unsigned long long)inner);
   const int64_t imask = inner - 1;
+  // twiddles w^t, t < Nv/2, after the tile (the stages read w^{pos N / 2^s} with
+  // pos < 2^{s-1})
+  uint32_t* twl = tile + total;
+  for (int t = threadIdx.x; t < Nv / 2; t += kBlock) twl[t] = w[t];
   // load: element j of local line l goes to tile[brev(j) * W + l]
   for (int idx = threadIdx.x; idx < total; idx += kBlock) {
     int j, l;
@@ -286,7 +300,7 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
       const int grp = b >> (s - 1), pos = b & (half - 1);
       const int i0 = grp * 2 * half + pos, i1 = i0 + half;
       const uint32_t u = tile[i0 * W + l];
-      const uint32_t v = mm(tile[i1 * W + l], w[pos * stride], p, pinv);
+      const uint32_t v = mm(tile[i1 * W + l], twl[pos * stride], p, pinv);
       tile[i0 * W + l] = addm(u, v, p);
       tile[i1 * W + l] = subm(u, v, p);
     }
@@ -462,9 +476,14 @@ hipError_t launch_expand_m(const MatPlan& P, const uint32_t* in, uint32_t* out, 
   const int64_t work = B * outer * (expand_jrange(P.N[v], P.m[v]) / JC) * inner;
   // the full evaluation tensor (last pass of the unfused path) is read without zero flags
   const bool write_zero = v == 0;
-  hipLaunchKernelGGL(expand_kernel<M>, dim3(blocks_for(work)), dim3(kBlock), 0, st, in, out, B,
-                     outer, P.m[v], P.N[v], JC, inner, P.nent, P.d_tw + P.tw_off[v], P.tw_stride,
-                     P.d_pc, P.d_zero, write_zero);
+  if (inner >= 64)
+    hipLaunchKernelGGL((expand_kernel<M, true>), dim3(blocks_for(work)), dim3(kBlock), 0, st, in,
+                       out, B, outer, P.m[v], P.N[v], JC, inner, P.nent, P.d_tw + P.tw_off[v],
+                       P.tw_stride, P.d_pc, P.d_zero, write_zero);
+  else
+    hipLaunchKernelGGL((expand_kernel<M, false>), dim3(blocks_for(work)), dim3(kBlock), 0, st, in,
+                       out, B, outer, P.m[v], P.N[v], JC, inner, P.nent, P.d_tw + P.tw_off[v],
+                       P.tw_stride, P.d_pc, P.d_zero, write_zero);
   return hipGetLastError();
 }
 
@@ -678,7 +697,7 @@ hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
     const int64_t lines = outer * inner;
     const int W = intt_lines_per_block(lines, Nv, P.pn);
     const int64_t tiles = (lines + W - 1) / W;
-    const size_t lds = (size_t)Nv * W * sizeof(uint32_t);
+    const size_t lds = (size_t)(Nv * W + Nv / 2) * sizeof(uint32_t);
     hipLaunchKernelGGL(intt_kernel, dim3((unsigned)(tiles * P.pn)), dim3(kBlock), lds, st, in, out,
                        outer, Nv, logN, inner, P.D[v] + 1, W, P.d_itw + P.tw_off[v], P.tw_stride,
                        P.d_pc);
