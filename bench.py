@@ -33,13 +33,14 @@ ALU_PEAK_UPDATES = CU * CLOCK_HZ * UPDATES_PER_CLK_CU
 # HBM bytes per launch of the fused elimination kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB copy (profiles/config2_hbm_traffic.md),
 # valid only for the kernel sources they were taken with (hash of det_impl.h + modarith.h).
-DET_TRAFFIC = {"sources_sha256_16": "430dfe8e2a1c663c", "bytes": 94.5e6 + 14.7e6}
+DET_TRAFFIC = {"sources_sha256_16": "f6075b04290cba9e", "bytes": 186.2e6 + 14.7e6}
 
 
 def kernel_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in ("paper_2010_12117_amd/csrc/det_impl.h", "paper_2010_12117_amd/csrc/modarith.h"):
+    for rel in ("paper_2010_12117_amd/csrc/det_impl.h", "paper_2010_12117_amd/csrc/modarith.h",
+                "paper_2010_12117_amd/tuning_gfx950.json"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -299,12 +300,20 @@ def main():
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    # one event between consecutive steps as well: the median step beside the mean
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps - 1)]
     e0.record(stream)
-    for _ in range(args.steps):
+    for i in range(args.steps):
         pdm.solve_device(pl, d_coeffs, out, ws)
+        if i < args.steps - 1:
+            marks[i].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
+    bounds = [e0] + marks + [e1]
+    step_ms = sorted(bounds[i].elapsed_time(bounds[i + 1]) for i in range(args.steps))
+    median_ms = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else \
+        0.5 * (step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2])
     stage_ms, solves = pl.stage_times()
     assert solves == args.steps
     ms_per_step = total_ms / args.steps
@@ -341,6 +350,7 @@ def main():
                    "n": n, "nvars": 3, "deg": list(deg), "grid": list(info["N"]), "primes": pn,
                    "nonzero_entries": nnz},
         "exact_dets_per_s": 1e3 / ms_per_step,
+        "ms_per_step_median": median_ms,
         "stage_ms": per,
         "roofline": dominant,
         "roofline_other": eval_roof if dominant is det_roof else det_roof,
