@@ -246,17 +246,24 @@ def test_det_mod_q_stack_matches_oracle_steps():
             assert int(got[t]) == OM.det_mod(A[t].astype(object).tolist(), Q31)
 
 
-def test_config4_all_matrices_identity_and_cheap_oracle():
-    """Every one of the 4096 matrices: the batched result, reduced mod an independent prime
-    q and evaluated at a seeded random point, equals det M(point) mod q (a false pass has
-    probability at most deg/q per matrix, Schwartz-Zippel). The cheapest matrices are also
-    compared with the oracle exactly."""
+@pytest.fixture(scope="module")
+def config4_solved():
+    """The 4096-matrix workload solved once in one batched call."""
     import torch
     mats = W.config4()
     pl = pdm.plan_batch(mats)
     d_coeffs, co, d_out, oo = pack(mats, pl)
     pdm.solve_batch_device(pl, d_coeffs, co, d_out, oo)
     torch.cuda.synchronize()
+    return mats, pl, d_out, oo
+
+
+def test_config4_all_matrices_identity_and_cheap_oracle(config4_solved):
+    """Every one of the 4096 matrices: the batched result, reduced mod an independent prime
+    q and evaluated at a seeded random point, equals det M(point) mod q (a false pass has
+    probability at most deg/q per matrix, Schwartz-Zippel). The cheapest matrices are also
+    compared with the oracle exactly."""
+    mats, pl, d_out, oo = config4_solved
     rng = np.random.default_rng(4242)
     q = Q31
     lhs, points = [], []
@@ -292,3 +299,44 @@ def test_config4_all_matrices_identity_and_cheap_oracle():
         n, deg = B.shape_of(mats[i])
         expect = OD.det_pointwise(mats[i], PL.det_degree_bound_from_shape(n, deg)).reshape(-1)
         assert vals == [int(x) for x in expect], i
+
+
+def test_config4_exact_integer_points_on_a_sample(config4_solved):
+    """A seeded sample of 48 of the 4096 matrices: at a random integer point a with
+    coordinates in [-2^20, 2^20], the batched result evaluated exactly (Python integers)
+    equals det M(a) from the oracle's integer Bareiss. A probabilistic identity check
+    (Schwartz-Zippel: a false pass has probability at most sum_v D_v / 2^21 per matrix), not
+    parity with the oracle's polynomial."""
+    mats, pl, d_out, oo = config4_solved
+    rng = np.random.default_rng(777)
+    small = [i for i, info in enumerate(pl.infos) if info["ncoeff"] <= 50000]
+    sample = sorted(int(i) for i in rng.choice(small, size=48, replace=False))
+    host = d_out.cpu().numpy()
+    for i in sample:
+        a, info, off = mats[i], pl.infos[i], oo[i]
+        n, deg = B.shape_of(a)
+        point = [int(x) for x in rng.integers(-(1 << 20), (1 << 20) + 1, size=len(deg))]
+        L = info["limbs"]
+        vals = B.limbs_to_ints(host[off:off + info["ncoeff"] * L].reshape(-1, L))
+        box = np.empty(len(vals), dtype=object)
+        box[:] = vals
+        box = box.reshape(tuple(d + 1 for d in info["D"]))
+        for v in range(len(deg) - 1, -1, -1):  # Horner along the last axis
+            acc = np.zeros(box.shape[:-1], dtype=object)
+            for e in range(box.shape[-1] - 1, -1, -1):
+                acc = acc * point[v] + box[..., e]
+            box = acc
+        got = int(box[()]) if isinstance(box, np.ndarray) else int(box)
+        M = []
+        for r in range(n):
+            row = []
+            for c in range(n):
+                ent = a[r, c].astype(object)
+                for v in range(len(deg) - 1, -1, -1):
+                    acc = np.zeros(ent.shape[:-1], dtype=object)
+                    for e in range(ent.shape[-1] - 1, -1, -1):
+                        acc = acc * point[v] + ent[..., e]
+                    ent = acc
+                row.append(int(ent[()]) if isinstance(ent, np.ndarray) else int(ent))
+            M.append(row)
+        assert got == OD.det_bareiss_int(M), i
