@@ -165,15 +165,17 @@ __device__ __forceinline__ DetFrac eliminate(uint32_t (&a)[(N + GL - 1) / GL][N]
   return f;
 }
 
-// Waves per SIMD asked of the compiler for the single-matrix paired kernel with one lane per
-// matrix. Left to itself the compiler lands a register or two above an occupancy step there
-// (169 at n = 12: two waves); the request is the lane's n^2 values plus kDetRegMargin, out
-// of 512 registers per lane, which gives 168 at n = 12 without spills. The other elimination
-// kernels need more than that margin (the request would spill) and get no request.
+// Waves per SIMD asked of the compiler for the single-matrix elimination kernels where it
+// lands just above an occupancy step by itself. With one lane per matrix (paired kernel) the
+// request is the lane's n^2 values plus kDetRegMargin, out of 512 registers per lane: 168 at
+// n = 12 (169 unasked: two waves) without spills. At n = 32 with 8 lanes (171-175 unasked)
+// three waves cost a few spilled values and were measured 7-8% faster; at n = 31 they were
+// not. Every other kernel gets no request (1: the launch bounds alone).
 constexpr int kDetRegMargin = 24;
-template <int N, int GL>
+template <int N, int GL, bool PAIR>
 constexpr int det_waves() {
-  if (GL != 1) return 1;  // 1: no constraint beyond the launch bounds
+  if (GL == 8 && N == 32) return 3;
+  if (GL != 1 || !PAIR) return 1;
   constexpr int regs = ((N * N + kDetRegMargin + 7) / 8) * 8;
   constexpr int w = 512 / regs;
   return w < 1 ? 1 : (w > 8 ? 8 : w);
@@ -420,7 +422,8 @@ __device__ __forceinline__ void det_fused_body(
 }
 
 template <int N, int GL>
-__global__ __launch_bounds__(kDetBlock) void det_fused_kernel(
+__global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_waves<N, GL, false>())))
+void det_fused_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
     int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
     const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, bool fixup) {
@@ -430,7 +433,7 @@ __global__ __launch_bounds__(kDetBlock) void det_fused_kernel(
 }
 
 template <int N, int GL>
-__global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_waves<N, GL>())))
+__global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_waves<N, GL, true>())))
 void det_fused_pair_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
     int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
