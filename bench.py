@@ -11,6 +11,7 @@ Prints one JSON line (see the repository's benchmark contract).
 """
 import argparse
 import json
+import math
 import multiprocessing as mp
 import os
 import sys
@@ -49,6 +50,20 @@ def kernel_sources_hash() -> str:
 def det_updates(n: int) -> int:
     """Elimination updates of one determinant: sum_{m=1}^{n-1} m^2."""
     return (n - 1) * n * (2 * n - 1) // 6
+
+
+def expand_bytes(pn: int, nnz: int, m, N) -> int:
+    """Algorithmic HBM bytes of the evaluation passes of one solve when the first variable is
+    evaluated inside the elimination kernel: the passes run over variables k-1 .. 1 of every
+    nonzero entry, each reading its input box and writing its output box (the residues
+    m_0 x .. x m_{k-1} first, the pre-tensor m_0 x N_1 x .. x N_{k-1} last)."""
+    shape = list(m)
+    words = 0
+    for v in range(len(m) - 1, 0, -1):
+        words += math.prod(shape)
+        shape[v] = N[v]
+        words += math.prod(shape)
+    return 4 * pn * nnz * words
 
 
 def cpu_baseline(arr, D, pn, G):
@@ -324,8 +339,7 @@ def main():
     nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
     det_work = pn * G * det_updates(n)
     det_achieved = det_work / (per["determinants"] / 1e3) / 1e12
-    m0 = deg[0] + 1
-    eval_bytes = pn * n * n * G * 4 + pn * n * n * m0 * (G // 64) * 4
+    eval_bytes = expand_bytes(pn, nnz, [d + 1 for d in deg], list(info["N"]))
     eval_gbs = eval_bytes / (per["evaluate"] / 1e3) / 1e9
     traffic = (DET_TRAFFIC["bytes"]
                if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)

@@ -340,3 +340,30 @@ def test_config4_exact_integer_points_on_a_sample(config4_solved):
                 row.append(int(ent[()]) if isinstance(ent, np.ndarray) else int(ent))
             M.append(row)
         assert got == OD.det_bareiss_int(M), i
+
+
+def test_config4_bit_exact_against_stored_oracle_digests(config4_solved):
+    """The cheapest three quarters of the 4096 matrices (by the pointwise oracle's cost): the
+    batched result equals the oracle's determinant exactly, compared through the digests that
+    tests/golden/make_config4_digests.py wrote from the oracle (canonical text of the nonzero
+    coefficients, SHA-256)."""
+    import json
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    from make_config4_digests import OUT, digest
+    stored = json.load(open(OUT))["digests"]
+    assert len(stored) >= 3000
+    mats, pl, d_out, oo = config4_solved
+    host = d_out.cpu().numpy()
+    bad = []
+    for key, want in stored.items():
+        i = int(key)
+        info, off = pl.infos[i], oo[i]
+        L = info["limbs"]
+        vals = B.limbs_to_ints(host[off:off + info["ncoeff"] * L].reshape(-1, L))
+        arr = np.empty(len(vals), dtype=object)
+        arr[:] = vals
+        box = tuple(d + 1 for d in info["D"])
+        if digest(arr.reshape(box) if box else arr.reshape(())) != want:
+            bad.append(i)
+    assert not bad, f"{len(bad)} matrices differ from the oracle, first {bad[:10]}"

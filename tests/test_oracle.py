@@ -156,6 +156,26 @@ def test_config2_shape_downscaled_oracles_agree():
     assert box_to_poly(B) == A
 
 
+def test_config4_digest_file_agrees_with_bareiss_over_polynomials():
+    """The stored digests of the batching workload (written from the pointwise oracle) match,
+    for the 24 cheapest matrices, the fraction-free Bareiss elimination over Z[x1..xk]: the
+    other realisation of the oracle, which shares no evaluation or interpolation code."""
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_config4_digests as MD
+    import hashlib
+    stored = json.load(open(MD.OUT))["digests"]
+    idx, shapes = MD.ranked_indices(0.75)
+    assert sorted(int(i) for i in stored) == sorted(idx)
+    mats = W.config4()
+    for i in idx[:24]:
+        a = mats[i]
+        n, k = a.shape[0], a.ndim - 2
+        A = OD.det_bareiss_poly(P.matrix_from_array(a, n, k), k)
+        text = ";".join(".".join(str(e) for e in key) + ":" + str(A[key]) for key in sorted(A))
+        assert hashlib.sha256(text.encode()).hexdigest()[:16] == stored[str(i)], i
+
+
 # ---------------------------------------------------------------------------------------
 # Closed forms
 # ---------------------------------------------------------------------------------------
