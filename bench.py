@@ -269,7 +269,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the determinant path is a single-GPU "
-              "kernel pipeline (see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "kernel pipeline, and no figure at several GPUs is measured", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "config4":

@@ -107,7 +107,9 @@ typedef struct polydet_shape {
 #define POLYDET_STAGE_TIMING ((uint32_t)1u << 30)
 
 /* reduce, evaluate, determinants (the elimination kernels: numerator and denominator per
- * point), finalize (det = num / den), interpolate, reconstruct */
+ * point), finalize (det = num / den), interpolate, reconstruct. When the matrix has
+ * variables the division is done by the first interpolation pass as it loads the points, and
+ * the finalize stage is empty (its time is counted in interpolate). */
 #define POLYDET_NUM_STAGES 6
 
 /* What a plan needs and produces. Workspace offsets (bytes) locate the intermediate stages

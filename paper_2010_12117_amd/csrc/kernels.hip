@@ -254,11 +254,21 @@ __global__ __launch_bounds__(kBlock) void finalize_batch_kernel(const BFinal* __
 // log2 Nv radix-2 decimation-in-time stages and writes the first D_v + 1 outputs of each line:
 //   in  [pn][outer][Nv][inner] -> out [pn][outer][Dv1][inner];  tile index = prime * tiles + t.
 // ------------------------------------------------------------------------------------
+//
+// With `den` set (the first pass, over the points' numerators and denominators), the load
+// also takes the division of the finalize step: each thread inverts the denominators of
+// kFuseBatch points with one exponentiation (simultaneous inversion), puts num / den in the
+// tile and writes it back over the numerator, so the workspace holds det mod p per point
+// as after a separate finalize launch.
+constexpr int kFuseBatch = 4;
+
 __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __restrict__ in,
                                           uint32_t* __restrict__ out, int64_t block,
                                           int64_t outer, int Nv, int logN, int64_t inner, int Dv1,
                                           int W, const uint32_t* __restrict__ itw,
-                                          int64_t tw_stride, const PrimeConst* __restrict__ pcs) {
+                                          int64_t tw_stride, const PrimeConst* __restrict__ pcs,
+                                          const uint32_t* __restrict__ den = nullptr,
+                                          uint32_t* quot = nullptr) {
   const int64_t lines = outer * inner;
   const int64_t tiles_per_prime = (lines + W - 1) / W;
   const int prime = (int)(block / tiles_per_prime);
@@ -278,20 +288,90 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
   uint32_t* twl = tile + total;
   for (int t = threadIdx.x; t < Nv / 2; t += kBlock) twl[t] = w[t];
   // load: element j of local line l goes to tile[brev(j) * W + l]
-  for (int idx = threadIdx.x; idx < total; idx += kBlock) {
-    int j, l;
-    if (inner >= W) { j = idx >> lW; l = idx & (W - 1); } else { l = idx >> logN; j = idx & (Nv - 1); }
-    uint32_t v = 0u;
-    if (l < nW) {
-      const int64_t line = line0 + l;
-      const int64_t o = line >> lI, q = line & imask;
-      v = src[(o * Nv + j) * inner + q];
+  if (den == nullptr) {
+    for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+      int j, l;
+      if (inner >= W) { j = idx >> lW; l = idx & (W - 1); } else { l = idx >> logN; j = idx & (Nv - 1); }
+      uint32_t v = 0u;
+      if (l < nW) {
+        const int64_t line = line0 + l;
+        const int64_t o = line >> lI, q = line & imask;
+        v = src[(o * Nv + j) * inner + q];
+      }
+      const int rj = logN ? (int)(__brev((unsigned)j) >> (32 - logN)) : 0;
+      tile[rj * W + l] = v;
     }
-    const int rj = logN ? (int)(__brev((unsigned)j) >> (32 - logN)) : 0;
-    tile[rj * W + l] = v;
+  } else {
+    const uint32_t one = pcs[prime].r1;
+    const int64_t poff = (int64_t)prime * outer * Nv * inner;
+    const uint32_t* dsrc = den + poff;
+    uint32_t* qdst = quot + poff;
+    for (int base = threadIdx.x; base < total; base += kFuseBatch * kBlock) {
+      uint32_t v[kFuseBatch], d[kFuseBatch], pre[kFuseBatch];
+      int64_t gi[kFuseBatch];
+      int ti[kFuseBatch];
+      uint32_t acc = one;
+#pragma unroll
+      for (int i = 0; i < kFuseBatch; ++i) {
+        const int idx = base + i * kBlock;
+        int j, l;
+        if (inner >= W) { j = idx >> lW; l = idx & (W - 1); } else { l = idx >> logN; j = idx & (Nv - 1); }
+        const int rj = logN ? (int)(__brev((unsigned)j) >> (32 - logN)) : 0;
+        ti[i] = idx < total ? rj * W + l : -1;
+        gi[i] = -1;
+        v[i] = 0u;
+        d[i] = one;
+        if (idx < total && l < nW) {
+          const int64_t line = line0 + l;
+          const int64_t o = line >> lI, q = line & imask;
+          gi[i] = (o * Nv + j) * inner + q;
+          v[i] = src[gi[i]];
+          d[i] = dsrc[gi[i]];
+        }
+        pre[i] = acc;  // product of the denominators before i
+        acc = mm(acc, d[i], p, pinv);
+      }
+      uint32_t inv = minv(acc, one, p, pinv);  // inverse of the product of all
+#pragma unroll
+      for (int i = kFuseBatch - 1; i >= 0; --i) {
+        const uint32_t di = mm(inv, pre[i], p, pinv);  // 1 / d[i]
+        inv = mm(inv, d[i], p, pinv);                   // 1 / (d[0] .. d[i-1])
+        const uint32_t qv = mm(v[i], di, p, pinv);
+        if (gi[i] >= 0) qdst[gi[i]] = qv;
+        if (ti[i] >= 0) tile[ti[i]] = qv;
+      }
+    }
   }
   __syncthreads();
-  for (int s = 1; s <= logN; ++s) {
+  int s = 1;
+  // Two stages per pass over the tile while two remain: a thread takes the four elements
+  // i0 + {0, h, 2h, 3h} (h = 2^{s-1}) that stages s and s+1 combine among themselves. Stage s
+  // pairs (0, h) and (2h, 3h) with the twiddle w^{pos N / 2^s}; stage s+1 pairs (0, 2h) with
+  // w^{pos N / 2^{s+1}} and (h, 3h) with w^{(pos + h) N / 2^{s+1}}. Half the barriers.
+  for (; s + 1 <= logN; s += 2) {
+    const int h = 1 << (s - 1);
+    const int st1 = Nv >> s, st2 = Nv >> (s + 1);
+    for (int bi = threadIdx.x; bi < (Nv / 4) * W; bi += kBlock) {
+      const int l = bi & (W - 1);
+      const int b = bi >> lW;
+      const int grp = b >> (s - 1), pos = b & (h - 1);
+      const int i0 = grp * 4 * h + pos;
+      uint32_t* e0 = tile + i0 * W + l;
+      const uint32_t x0 = e0[0], x1 = e0[h * W], x2 = e0[2 * h * W], x3 = e0[3 * h * W];
+      const uint32_t t1 = twl[pos * st1];
+      const uint32_t v1 = mm(x1, t1, p, pinv), v3 = mm(x3, t1, p, pinv);
+      const uint32_t u0 = addm(x0, v1, p), u1 = subm(x0, v1, p);
+      const uint32_t u2 = addm(x2, v3, p), u3 = subm(x2, v3, p);
+      const uint32_t y2 = mm(u2, twl[pos * st2], p, pinv);
+      const uint32_t y3 = mm(u3, twl[(pos + h) * st2], p, pinv);
+      e0[0] = addm(u0, y2, p);
+      e0[2 * h * W] = subm(u0, y2, p);
+      e0[h * W] = addm(u1, y3, p);
+      e0[3 * h * W] = subm(u1, y3, p);
+    }
+    __syncthreads();
+  }
+  for (; s <= logN; ++s) {  // the last stage when log2 Nv is odd
     const int half = 1 << (s - 1);
     const int stride = Nv >> s;  // twiddle index step: w^{pos * N / 2^s}
     for (int bi = threadIdx.x; bi < (Nv / 2) * W; bi += kBlock) {
@@ -321,9 +401,10 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
 __global__ __launch_bounds__(kBlock) void intt_kernel(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t outer, int Nv, int logN,
     int64_t inner, int Dv1, int W, const uint32_t* __restrict__ itw, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs) {
+    const PrimeConst* __restrict__ pcs, const uint32_t* __restrict__ den, uint32_t* quot) {
   extern __shared__ uint32_t tile[];  // [Nv][W]
-  intt_body(tile, in, out, blockIdx.x, outer, Nv, logN, inner, Dv1, W, itw, tw_stride, pcs);
+  intt_body(tile, in, out, blockIdx.x, outer, Nv, logN, inner, Dv1, W, itw, tw_stride, pcs, den,
+            quot);
 }
 
 __global__ __launch_bounds__(kBlock) void intt_batch_kernel(const BIntt* __restrict__ desc,
@@ -676,6 +757,8 @@ hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st) {
 }
 
 hipError_t run_finalize(const MatPlan& P, uint8_t* ws, hipStream_t st) {
+  // with variables the first interpolation pass divides as it loads (intt_body)
+  if (P.k > 0) return hipSuccess;
   hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(finalize_threads(P.G, P.pn))), dim3(kBlock),
                      0, st, (uint32_t*)(ws + P.off_detv), (const uint32_t*)(ws + P.off_den), P.G,
                      P.pn, P.d_pc);
@@ -699,9 +782,12 @@ hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
     const int W = intt_lines_per_block(lines, Nv, P.pn);
     const int64_t tiles = (lines + W - 1) / W;
     const size_t lds = (size_t)(Nv * W + Nv / 2) * sizeof(uint32_t);
+    // the first pass also divides each point's numerator by its denominator
+    const uint32_t* den = v == 0 ? (const uint32_t*)(ws + P.off_den) : nullptr;
+    uint32_t* quot = v == 0 ? (uint32_t*)(ws + P.off_detv) : nullptr;
     hipLaunchKernelGGL(intt_kernel, dim3((unsigned)(tiles * P.pn)), dim3(kBlock), lds, st, in, out,
                        outer, Nv, logN, inner, P.D[v] + 1, W, P.d_itw + P.tw_off[v], P.tw_stride,
-                       P.d_pc);
+                       P.d_pc, den, quot);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     in = out;
