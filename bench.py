@@ -33,8 +33,8 @@ ALU_PEAK_UPDATES = CU * CLOCK_HZ * UPDATES_PER_CLK_CU
 
 # HBM bytes per launch of the fused elimination kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB copy (profiles/config2_hbm_traffic.md),
-# valid only for the kernel sources they were taken with (hash of det_impl.h + modarith.h).
-DET_TRAFFIC = {"sources_sha256_16": "f6075b04290cba9e", "bytes": 186.2e6 + 14.7e6}
+# valid only for the kernel sources and tuning table they were taken with (their hash).
+DET_TRAFFIC = {"sources_sha256_16": "99fc407706dbe28c", "bytes": 186.2e6 + 14.7e6}
 
 
 def kernel_sources_hash() -> str:
@@ -248,8 +248,10 @@ def det_kernel_name(info):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 200 solves at config 2, 2 batch solves at config 4)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default: 20 at config 2, 1 at config 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="config2", choices=["config2", "config4", "config5"],
                     help="config2: the 12x12 trivariate matrix (default); config4: the batch "
@@ -272,6 +274,11 @@ def main():
               "kernel pipeline, and no figure at several GPUs is measured", file=sys.stderr)
         sys.exit(2)
 
+    big = args.workload == "config4"
+    if args.steps is None:
+        args.steps = 2 if big else 200
+    if args.warmup is None:
+        args.warmup = 1 if big else 20
     if args.workload == "config4":
         bench_batch(args)
         return
@@ -287,12 +294,16 @@ def main():
 
     arr = W.config2()
     n, deg = 12, (3, 3, 3)
-    flags = pdm.STAGE_TIMING
+    flags = 0
     if args.det_lanes:
         flags |= pdm.DET_LANES_LOG2(args.det_lanes.bit_length() - 1)
     flags |= {"auto": 0, "left-looking": pdm.DET_LEFT_LOOKING,
               "exchange": pdm.DET_EXCHANGE}[args.det_form]
+    # the timed plan records no stage events (each costs a few microseconds of device time
+    # between the kernels); a second plan with the library's stage events gives the kernels'
+    # own durations over a second pass of the same number of solves
     pl = pdm.plan(n, deg, host_coeffs=arr, flags=flags)
+    pl_stages = pdm.plan(n, deg, host_coeffs=arr, flags=flags | pdm.STAGE_TIMING)
     info = pl.info
     pn, G = info["pn"], info["G"]
     dev = torch.device("cuda:0")
@@ -310,28 +321,33 @@ def main():
     for _ in range(args.warmup):
         pdm.solve_device(pl, d_coeffs, out, ws)
     torch.cuda.synchronize()
-    pl.stage_times()  # discard warm-up stage times
 
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    # one event between consecutive steps as well: the median step beside the mean
-    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps - 1)]
     e0.record(stream)
     for i in range(args.steps):
         pdm.solve_device(pl, d_coeffs, out, ws)
-        if i < args.steps - 1:
-            marks[i].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
-    bounds = [e0] + marks + [e1]
-    step_ms = sorted(bounds[i].elapsed_time(bounds[i + 1]) for i in range(args.steps))
-    median_ms = step_ms[len(step_ms) // 2] if len(step_ms) % 2 else \
-        0.5 * (step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2])
-    stage_ms, solves = pl.stage_times()
-    assert solves == args.steps
     ms_per_step = total_ms / args.steps
+
+    # the same solves again with stage events: the duration of each stage's kernels
+    for _ in range(max(1, args.warmup // 4)):
+        pdm.solve_device(pl_stages, d_coeffs, out, ws)
+    torch.cuda.synchronize()
+    pl_stages.stage_times()  # discard the warm-up solves
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for i in range(args.steps):
+        pdm.solve_device(pl_stages, d_coeffs, out, ws)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    staged_ms_per_step = s0.elapsed_time(s1) / args.steps
+    stage_ms, solves = pl_stages.stage_times()
+    assert solves == args.steps
     value = pn * G / (ms_per_step / 1e3)
 
     # roofline of each kernel class from its measured average duration
@@ -364,7 +380,7 @@ def main():
                    "n": n, "nvars": 3, "deg": list(deg), "grid": list(info["N"]), "primes": pn,
                    "nonzero_entries": nnz},
         "exact_dets_per_s": 1e3 / ms_per_step,
-        "ms_per_step_median": median_ms,
+        "ms_per_step_with_stage_events": staged_ms_per_step,
         "stage_ms": per,
         "roofline": dominant,
         "roofline_other": eval_roof if dominant is det_roof else det_roof,
