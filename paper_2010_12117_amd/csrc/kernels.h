@@ -22,7 +22,9 @@ int64_t finalize_threads(int64_t G, int pn);  // threads of the det = num / den 
 hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st);
 hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st);
 hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st);       // numerators, denominators
-hipError_t run_finalize(const MatPlan& P, uint8_t* ws, hipStream_t st);  // det = num / den
+// det = num / den: a launch of its own only without variables; otherwise run_interpolate's
+// first pass divides as it loads
+hipError_t run_finalize(const MatPlan& P, uint8_t* ws, hipStream_t st);
 hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st);
 hipError_t run_reconstruct(const MatPlan& P, uint8_t* ws, uint32_t* out, hipStream_t st);
 
