@@ -314,3 +314,22 @@ def test_prime_range_and_reconstruct_reject_bad_arguments():
     assert lib.polydet_solve_primes(None, dummy, 0, 1, dummy, ws, None) == B.EINVAL
     bp = pdm.plan_batch(W.config4(count=4), flags=pdm.HOST_ONLY)
     assert lib.polydet_solve_primes(bp.handle, dummy, 0, 1, dummy, 1 << 40, None) == B.EINVAL
+
+
+def test_bench_algorithmic_figures():
+    """bench.py's per-unit figures: elimination updates per determinant (sum of m^2 for
+    m < n, 506 at n = 12, checked by counting the (n-k-1)^2 updates of each step) and the
+    bytes of the evaluation passes at the 12x12 trivariate workload (7 primes, 101 nonzero
+    entries): residues 4^3, pass over x3 writes 4^2 x 64 and the next reads it, the
+    pre-tensor 4 x 64^2, 4 bytes each."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "bench_under_test", os.path.join(os.path.dirname(os.path.dirname(__file__)), "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    for n in range(1, 33):
+        assert bench.det_updates(n) == sum((n - k - 1) ** 2 for k in range(n))
+    assert bench.det_updates(12) == 506
+    assert bench.expand_bytes(7, 101, [4, 4, 4], [64, 64, 64]) == 4 * 7 * 101 * (64 + 2 * 1024 + 16384)
+    assert bench.expand_bytes(3, 5, [2], [8]) == 0  # one variable: evaluated inside the elimination
