@@ -145,7 +145,7 @@ def bench_batch(args):
         "value": moddets / (ms_batched / 1e3), "unit": "modular dets/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batched,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32 (mod p < 2^31)", "data": "synthetic (seeded)",
+        "dtype": "u32 (mod p < 2^30)", "data": "synthetic (seeded)",
         "config": {"workload": f"{len(mats)} matrices, n 4..24, 2-3 variables, degree 1-4, "
                                "10-40% zero entries, coefficients U[-4096,4096]",
                    "matrices": len(mats), "modular_dets": moddets, "updates": updates,
@@ -373,7 +373,7 @@ def main():
         "metric": "modular dets/sec (prime x point), exact poly det end to end, 1 GPU",
         "value": value, "unit": "modular dets/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32 (mod p < 2^31)",
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32 (mod p < 2^30)",
         "data": "synthetic (seeded)",
         "config": {"workload": "12x12 trivariate degree-3 matrix, coefficients U[-1000,1000], "
                                "30% zero entries, 64^3 grid, 7 primes",
