@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
 // r and so j, the prime and the entry; they are taken from the wave's first index, which lets
 // the twiddle, constant and zero-flag loads be scalar.
 // ------------------------------------------------------------------------------------
-template <int M, bool UJ>
+template <int M, bool UJ, bool EXACT>
 __device__ __forceinline__ void expand_body(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t idx, int64_t B,
     int64_t outer, int m, int Nv, int JC, int64_t inner, int64_t nent,
@@ -139,13 +139,18 @@ __device__ __forceinline__ void expand_body(
   for (int e = 0; e < M; ++e) x[e] = e < m ? src[(int64_t)e * inner] : 0u;
   const int mask = Nv - 1;
   if (paired) {
+    // unrolled so that the twiddle loads of several points are in flight together
+#pragma unroll 4
     for (int j = j0; j < j0 + JC; ++j) {
       // E = x0 + (x2 w^2j + x4 w^4j) + ..., O = (x1 w^j + x3 w^3j) + ..., two per reduction
+      // With EXACT (m == M) the loop over e has no runtime condition, and the twiddle loads
+      // of the unrolled points are issued together. Otherwise the terms past m - 1 (x[e] = 0,
+      // adding nothing) are skipped.
       uint32_t E = x[0], O = 0u;
 #pragma unroll
       for (int e = 2; e < M; e += 4) {
-        if (e < m) {
-          if (e + 2 < M && e + 2 < m)
+        if (EXACT || e < m) {
+          if (e + 2 < M && (EXACT || e + 2 < m))
             E = addm(E, mm2(x[e], w[(e * j) & mask], x[e + 2], w[((e + 2) * j) & mask], p, pinv), p);
           else
             E = addm(E, mm(x[e], w[(e * j) & mask], p, pinv), p);
@@ -153,8 +158,8 @@ __device__ __forceinline__ void expand_body(
       }
 #pragma unroll
       for (int e = 1; e < M; e += 4) {
-        if (e < m) {
-          if (e + 2 < M && e + 2 < m)
+        if (EXACT || e < m) {
+          if (e + 2 < M && (EXACT || e + 2 < m))
             O = addm(O, mm2(x[e], w[(e * j) & mask], x[e + 2], w[((e + 2) * j) & mask], p, pinv), p);
           else
             O = addm(O, mm(x[e], w[(e * j) & mask], p, pinv), p);
@@ -176,7 +181,8 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
     int64_t tw_stride, const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
     bool write_zero) {
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  expand_body<M, UJ>(in, out, idx, B, outer, m, Nv, JC, inner, nent, tw, tw_stride, pcs, zero,
+  // the single-matrix launches pick M = m up to 8 (launch_expand)
+  expand_body<M, UJ, (M <= 8)>(in, out, idx, B, outer, m, Nv, JC, inner, nent, tw, tw_stride, pcs, zero,
                      write_zero);
 }
 
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __r
   for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
     const BExpand& d = desc[find_desc(desc, ndesc, vb)];
     const int64_t idx = (vb - d.block0) * kBlock + threadIdx.x;
-    expand_body<kBatchMaxM, false>((const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), idx,
+    expand_body<kBatchMaxM, false, false>((const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), idx,
                             d.B, d.outer, d.m, d.Nv, d.JC, d.inner, d.nent, d.tw, d.tw_stride,
                             d.pc, d.zero, false);
   }
