@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void finalize_batch_kernel(const BFinal* __
 // kFuseBatch points with one exponentiation (simultaneous inversion), puts num / den in the
 // tile and writes it back over the numerator, so the workspace holds det mod p per point
 // as after a separate finalize launch.
-constexpr int kFuseBatch = 4;
+constexpr int kFuseBatch = 8;
 
 __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __restrict__ in,
                                           uint32_t* __restrict__ out, int64_t block,
@@ -785,7 +785,11 @@ hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
     int logN = 0;
     while ((1 << logN) < Nv) ++logN;
     const int64_t lines = outer * inner;
-    const int W = intt_lines_per_block(lines, Nv, P.pn);
+    int W = intt_lines_per_block(lines, Nv, P.pn);
+    // the dividing first pass: enough lines that each thread has kFuseBatch points to invert
+    // together (at 64^3 that halves the exponentiations; measured 2 us faster)
+    if (v == 0)
+      while (Nv * W < kFuseBatch * kBlock && Nv * (2 * W) <= kTileElems) W <<= 1;
     const int64_t tiles = (lines + W - 1) / W;
     const size_t lds = (size_t)(Nv * W + Nv / 2) * sizeof(uint32_t);
     // the first pass also divides each point's numerator by its denominator
