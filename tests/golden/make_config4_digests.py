@@ -5,9 +5,10 @@ The workload is the seeded generator's (n uniform in [4, 24], 2-3 variables, per
 degree 1-4, coefficients uniform in [-2^12, 2^12], 10-40% zero entries). Matrices are ranked by
 the pointwise oracle's cost, prod_v (n d_v + 1) nodes times n^3, and the cheapest `--fraction`
 of them are solved by the oracle's pointwise Bareiss (evaluation at integer nodes, integer
-Bareiss per node, exact Newton interpolation). Each result is stored as the first 16 hex digits
-of the SHA-256 of its canonical text (see `canonical_text`), which does not depend on the box
-the coefficients are laid out in.
+Bareiss per node, exact interpolation through the integer-scaled inverse Vandermonde
+matrix). Each result is stored as the first 16 hex digits of the SHA-256 of its canonical
+text (see `canonical_text`), which does not depend on the box the coefficients are laid out
+in.
 
 Only the oracle and the seeded input generator are used. Usage:
     python tests/golden/make_config4_digests.py [--fraction 0.75] [--workers 7]

@@ -455,3 +455,43 @@ def test_modular_stage_values_match_oracle_polynomial():
         p = pp["p"]
         for j in itertools.product(*[range(x) for x in info["N"]]):
             assert pp["dets"][j] == OM.evaluate_at_node(exact, p, pp["omegas"], j)
+
+
+def test_evaluation_exponent_sign_and_root_against_sympy_ntt():
+    # the node j of variable v is w_v^{+j}: evaluating x alone at node 1 gives w itself, and a
+    # dense univariate entry at every node equals sympy's number-theoretic transform (which
+    # takes the same root, the least primitive root raised to (p-1)/N)
+    from sympy.discrete.transforms import intt, ntt
+    p = PL.ntt_primes(3)[2]
+    for N in (4, 16):
+        w = PL.root_of_unity(p, N)
+        assert OM.evaluate_at_node({(1,): 1}, p, [w], [1]) == w
+        assert OM.evaluate_at_node({(1,): 1}, p, [w], [3]) == pow(w, 3, p)
+        rng = random.Random(N)
+        coeffs = [rng.randrange(p) for _ in range(N)]
+        f = {(e,): c for e, c in enumerate(coeffs)}
+        vals = [OM.evaluate_at_node(f, p, [w], [j]) for j in range(N)]
+        assert vals == [int(x) for x in ntt(coeffs, p)]
+        back = OM.interpolate_mod(np.array(vals, dtype=object), p, [w])
+        assert [int(x) for x in back] == [int(x) for x in intt(vals, p)] == coeffs
+    # bivariate: x y^2 at (j1, j2) is w1^j1 w2^(2 j2)
+    w1, w2 = PL.root_of_unity(p, 8), PL.root_of_unity(p, 4)
+    assert OM.evaluate_at_node({(1, 2): 1}, p, [w1, w2], [3, 1]) == pow(w1, 3, p) * pow(w2, 2, p) % p
+
+
+def test_limbs_for_is_the_twos_complement_width():
+    # L limbs hold every x with |x| <= (M-1)/2 as a two's-complement integer of 32 L bits, and
+    # L - 1 limbs do not (Python's own signed encoding is the reference)
+    ps = PL.ntt_primes(5)
+    prods = [1]
+    for p in ps:
+        prods.append(prods[-1] * p)
+    for M in [3, 2 ** 32 - 1, 2 ** 32 + 1, 2 ** 33 - 1, 2 ** 64 - 1, 2 ** 64 + 1, 2 ** 96 + 3] + prods[1:]:
+        L = PL.limbs_for(M)
+        half = (M - 1) // 2
+        for x in (half, -half):
+            x.to_bytes(4 * L, "little", signed=True)
+        if L > 1:
+            with pytest.raises(OverflowError):
+                half.to_bytes(4 * (L - 1), "little", signed=True)
+    assert PL.limbs_for(2 ** 32 - 1) == 1 and PL.limbs_for(2 ** 32 + 1) == 2
