@@ -151,9 +151,15 @@ typedef struct polydet_plan_info {
 typedef struct polydet_plan_s* polydet_plan_t;
 
 /* Build a plan for one matrix shape.
- * host_coeffs: NULL, or the int64 coefficients on the host in the input layout; with them
- *   the bound B is computed from the data (fewer primes), without them from coeff_bits.
- *   Only pn and limbs depend on this choice; the coefficients of the result do not.
+ * host_coeffs: NULL, or the int64 coefficients on the host in the input layout. Without
+ *   them the plan holds for every matrix of the shape whose coefficients are at most
+ *   2^coeff_bits in absolute value. With them the plan is specialised to those coefficients:
+ *   the bound B comes from their 1-norms (fewer primes), their zero entries are skipped by
+ *   the kernels (never read), and the rows are reordered around structurally zero pivots
+ *   (row_order, det_sign). Such a plan is valid only for matrices with exactly that zero
+ *   pattern whose entries' 1-norms are no larger; solving any other coefficient tensor with
+ *   it returns a wrong determinant, which polydet_solve cannot detect. For a valid input
+ *   the result does not depend on the choice: only pn and limbs do.
  * Returns EINVAL for n < 1, nvars outside 0..8, a negative degree or coeff_bits outside
  * 0..63; EUNSUPPORTED beyond polydet_limits; EDEVICE/ENOMEM when uploading tables fails.
  * The plan's tables live on the device that is current when it is built. */

@@ -333,3 +333,22 @@ def test_bench_algorithmic_figures():
     assert bench.det_updates(12) == 506
     assert bench.expand_bytes(7, 101, [4, 4, 4], [64, 64, 64]) == 4 * 7 * 101 * (64 + 2 * 1024 + 16384)
     assert bench.expand_bytes(3, 5, [2], [8]) == 0  # one variable: evaluated inside the elimination
+
+
+def test_plan_with_coefficients_is_specialised_to_their_zero_pattern():
+    # the header's contract: a plan built from host coefficients skips their zero entries and
+    # reorders rows around structurally zero pivots; without coefficients it does neither and
+    # holds for every matrix of the shape within coeff_bits
+    rng = np.random.default_rng(12)
+    arr = W.random_matrix(rng, 5, (1, 1), -9, 9)
+    arr[0, 0] = 0
+    arr[1, 0] = 0
+    spec = pdm.plan(5, (1, 1), host_coeffs=arr, flags=pdm.HOST_ONLY).info
+    generic = pdm.plan(5, (1, 1), coeff_bits=4, flags=pdm.HOST_ONLY).info
+    assert spec["row_order"][0] == 2 and spec["det_sign"] == -1
+    assert generic["row_order"] == tuple(range(5)) and generic["det_sign"] == 1
+    assert generic["pn"] >= spec["pn"]
+    # the row order depends on the zero pattern, not on the values
+    other = arr * 3
+    assert pdm.plan(5, (1, 1), host_coeffs=other, flags=pdm.HOST_ONLY).info["row_order"] == \
+        spec["row_order"]
