@@ -36,12 +36,12 @@ FLAGS = [
 
 
 def _units():
-    units = [
-        ("plan.o", os.path.join(CSRC, "plan.cpp"), []),
-        ("polydet.o", os.path.join(CSRC, "polydet.cpp"), []),
-        ("batch_plan.o", os.path.join(CSRC, "batch_plan.cpp"), []),
-        ("kernels.o", os.path.join(CSRC, "kernels.hip"), []),
-    ]
+    # every host source and every HIP source of csrc/ (det_part.hip once per slice)
+    units = []
+    for name in sorted(os.listdir(CSRC)):
+        stem, ext = os.path.splitext(name)
+        if ext in (".cpp", ".hip") and name != "det_part.hip":
+            units.append((stem + ".o", os.path.join(CSRC, name), []))
     for part in range(DET_PARTS):
         units.append((f"det_part{part}.o", os.path.join(CSRC, "det_part.hip"),
                       [f"-DDET_PART={part}"]))
