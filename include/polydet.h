@@ -119,8 +119,15 @@ typedef struct polydet_shape {
  *              (x * 2^32 mod p); point index = natural multi-index (j_1 slowest), node
  *              (w_1^j_1, ..., w_k^j_k) with w_v = g^((p-1)/N[v]), g the least primitive
  *              root mod p;
- *   off_detv : uint32 [pn][G]        determinant at each grid point, Montgomery form;
- *   off_coef : uint32 [pn][ncoeff]   coefficients of det M mod p, Montgomery form. */
+ *   off_detv : uint32 [pn][G]        numerator of the determinant at each grid point and
+ *   off_den  : uint32 [pn][G]        its denominator (never 0), both Montgomery form: the
+ *              determinant mod p at the point is num / den (the elimination takes one
+ *              inverse per point, in the next stage);
+ *   off_coef : uint32 [pn][ncoeff]   coefficients of det M mod p, Montgomery form, times G
+ *              (the interpolation's 1/G is applied by the reconstruction); for nvars = 0,
+ *              ncoeff = 1 and this is the determinant residue itself.
+ * Every stage reads only the outputs of earlier stages, so any stage of a finished solve can
+ * be run again on the same workspace (polydet_solve_stages) with the same result. */
 typedef struct polydet_plan_info {
   int32_t n, nvars;
   int32_t deg[POLYDET_MAX_VARS];
@@ -146,6 +153,10 @@ typedef struct polydet_plan_info {
   int32_t prime_group;      /* primes per pass of S1-S4 (pn unless the workspace is capped) */
   size_t coef_bytes;        /* 4 * pn * ncoeff: the coefficient residues at off_coef, prime
                              * major ([pn][ncoeff], Montgomery form, factor G left in) */
+  size_t off_den;           /* see above */
+  int64_t nslots;           /* entries that are reduced and evaluated: with host_coeffs, the
+                             * distinct nonzero entries (entries with equal coefficient boxes,
+                             * as in Sylvester matrices, are evaluated once); otherwise n*n */
 } polydet_plan_info;
 
 typedef struct polydet_plan_s* polydet_plan_t;
@@ -212,6 +223,19 @@ polydet_status polydet_solve_batch(polydet_plan_t plan, const int64_t* d_coeffs,
                                    const int64_t* out_offsets, void* d_workspace,
                                    size_t workspace_bytes, void* stream);
 
+/* Stages [stage_begin, stage_end) of polydet_solve, numbered as in polydet_stage_times
+ * (0 reduce, 1 evaluate, 2 determinants, 3 finalize, 4 interpolate, 5 reconstruct), for a
+ * single-matrix plan that solves all its primes at once (prime_group == pn). The stages before
+ * stage_begin must have run on this workspace (with the same coefficients) earlier on the
+ * stream; running stages [0, s) and then [s, 6) gives exactly polydet_solve's result, and a
+ * stage may be run again (each reads only earlier stages' outputs), e.g. to time one kernel
+ * by itself. d_coeffs is read only when stage 0 is included, d_out written only when stage 5
+ * is. With POLYDET_STAGE_TIMING the call counts as one solve whose stages outside the range
+ * took no time. EINVAL for an empty or out-of-range interval, a batch or capped plan. */
+polydet_status polydet_solve_stages(polydet_plan_t plan, int32_t stage_begin, int32_t stage_end,
+                                    const int64_t* d_coeffs, uint32_t* d_out, void* d_workspace,
+                                    size_t workspace_bytes, void* stream);
+
 /* The solve of a single-matrix plan in two parts, for callers that checkpoint, resume or
  * cancel long solves between primes:
  *   polydet_solve_primes runs S1-S4 for primes [prime_begin, prime_end) (0 <= begin < end
@@ -234,7 +258,10 @@ polydet_status polydet_reconstruct(polydet_plan_t plan, void* d_workspace,
  * paper's tables report the same split: FFT, DET, IFFT, CRT). Waits for the recorded
  * solves, writes the summed milliseconds of each stage (POLYDET_NUM_STAGES of them, in the
  * order listed there) to ms[] and the number of solves to *solves, and resets the sums.
- * EINVAL if the plan was made without the flag. */
+ * Single-matrix plans record an event at each stage boundary. Batch plans (batched launches)
+ * record an event before and after every launch and add its time to the stage of its kind
+ * (matrices solved one by one after the batched launches are not included). EINVAL if the
+ * plan was made without the flag. */
 polydet_status polydet_stage_times(polydet_plan_t plan, double ms[POLYDET_NUM_STAGES],
                                    int64_t* solves);
 

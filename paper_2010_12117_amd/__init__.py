@@ -10,11 +10,11 @@ from .binding import (DET_LANES_LOG2, FORCE_PN, HOST_ONLY, PRIME_OFFSET, STAGE_T
                       Plan, PolydetError,
                       coefficient_region, det, get_tuning, limbs_to_ints, limits, load_library,
                       plan, plan_batch, reconstruct_device, set_tuning, solve_batch_device,
-                      solve_device, solve_primes_device)
+                      solve_device, solve_primes_device, solve_stages_device)
 
 __all__ = ["DET_LANES_LOG2", "FORCE_PN", "HOST_ONLY", "PRIME_OFFSET", "STAGE_TIMING", "STAGES",
            "UNFUSED_EVAL", "BATCH_PLAIN", "DET_LEFT_LOOKING", "DET_EXCHANGE",
            "Plan", "PolydetError",
            "coefficient_region", "det", "get_tuning", "limbs_to_ints", "limits", "load_library",
            "plan", "plan_batch", "reconstruct_device", "set_tuning", "solve_batch_device",
-           "solve_device", "solve_primes_device"]
+           "solve_device", "solve_primes_device", "solve_stages_device"]

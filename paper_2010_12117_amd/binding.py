@@ -64,7 +64,8 @@ class PlanInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("off_eval", ctypes.c_size_t),
                 ("off_detv", ctypes.c_size_t), ("off_coef", ctypes.c_size_t),
                 ("row_order", ctypes.c_uint8 * 32), ("det_left_looking", ctypes.c_int32),
-                ("prime_group", ctypes.c_int32), ("coef_bytes", ctypes.c_size_t)]
+                ("prime_group", ctypes.c_int32), ("coef_bytes", ctypes.c_size_t),
+                ("off_den", ctypes.c_size_t), ("nslots", ctypes.c_int64)]
 
 
 TUNE_ORDERS = 33
@@ -81,7 +82,8 @@ EXPORTS = ["polydet_plan", "polydet_plan_batch", "polydet_plan_query", "polydet_
            "polydet_solve", "polydet_solve_batch", "polydet_plan_destroy",
            "polydet_status_string", "polydet_last_error", "polydet_limits",
            "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning",
-           "polydet_plan_capped", "polydet_solve_primes", "polydet_reconstruct"]
+           "polydet_plan_capped", "polydet_solve_primes", "polydet_reconstruct",
+           "polydet_solve_stages"]
 
 _lib = None
 
@@ -125,10 +127,12 @@ def load_library(path: str = LIB_PATH):
     lib.polydet_plan_capped.argtypes = [ctypes.POINTER(Shape), vp, u32, sz, ctypes.POINTER(vp)]
     lib.polydet_solve_primes.argtypes = [vp, vp, i32, i32, vp, sz, vp]
     lib.polydet_reconstruct.argtypes = [vp, vp, sz, vp, vp]
+    lib.polydet_solve_stages.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
     for name in ["polydet_plan", "polydet_plan_batch", "polydet_plan_query",
                  "polydet_plan_primes", "polydet_solve", "polydet_solve_batch",
                  "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning",
-                 "polydet_plan_capped", "polydet_solve_primes", "polydet_reconstruct"]:
+                 "polydet_plan_capped", "polydet_solve_primes", "polydet_reconstruct",
+           "polydet_solve_stages"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     _install_default_tuning()
@@ -336,6 +340,18 @@ def solve_device(pl: Plan, d_coeffs, d_out=None, workspace=None, stream=None):
                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                              _stream_ptr(torch, stream)))
     return d_out, workspace
+
+
+def solve_stages_device(pl: Plan, stage_begin: int, stage_end: int, d_coeffs, d_out, workspace,
+                        stream=None):
+    """Enqueue polydet_solve_stages: stages [stage_begin, stage_end) of a solve (STAGES order)
+    on a workspace that holds the earlier stages' outputs."""
+    torch = _torch()
+    lib = load_library()
+    ptr = (lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None)
+    _check(lib.polydet_solve_stages(pl.handle, int(stage_begin), int(stage_end), ptr(d_coeffs),
+                                    ptr(d_out), ctypes.c_void_p(workspace.data_ptr()),
+                                    workspace.numel(), _stream_ptr(torch, stream)))
 
 
 def solve_primes_device(pl: Plan, d_coeffs, prime_begin: int, prime_end: int, workspace,

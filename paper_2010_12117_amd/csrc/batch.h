@@ -21,12 +21,12 @@ namespace pd {
 
 struct BReduce {
   int64_t block0;  // first virtual block of this matrix
-  int64_t count;   // n * n * T coefficients
+  int64_t count;   // nslot * T coefficients
   int64_t T;
   int64_t res_off;
-  int32_t mat, n, pn, pad;
+  int32_t mat, pn;
   const PrimeConst* pc;
-  const int32_t* rowdest;
+  const int32_t* slot_src;
 };
 
 struct BExpand {
@@ -40,11 +40,12 @@ struct BExpand {
 
 struct BDet {
   int64_t block0;
-  int64_t pre_off, detv_off, den_off, R, tw_stride, rtiles, jtiles;
+  int64_t pre_off, detv_off, den_off, R, tw_stride, rtiles, jtiles, nslot;
   int32_t N0, m0, Q, S;
   const uint32_t* tw0;
   const PrimeConst* pc;
   const uint8_t* zero;
+  const int32_t* slot;
 };
 
 struct BFinal {

@@ -31,16 +31,17 @@ Regions regions_of(const MatPlan& P, size_t base) {
     return o;
   };
   const size_t pn = P.pn;
-  r.res = take(pn * P.nent * P.T * 4);
-  size_t inter = 0;
+  r.res = take(pn * std::max<int64_t>(P.nslot, 1) * P.T * 4);
+  size_t interAB[2] = {0, 0};  // passes over variables k-1 .. 1 write tmpA, tmpB, ... in turn
   for (int v = P.k - 1; v >= 1; --v) {
     int64_t sz = 1;
     for (int u = 0; u < v; ++u) sz *= P.m[u];
     for (int u = v; u < P.k; ++u) sz *= P.N[u];
-    inter = std::max(inter, (size_t)sz);
+    const int which = (P.k - 1 - v) % 2;
+    interAB[which] = std::max(interAB[which], (size_t)sz);
   }
-  r.tmpA = take(pn * P.nent * inter * 4);
-  r.tmpB = take(pn * P.nent * inter * 4);
+  r.tmpA = take(pn * P.nslot * interAB[0] * 4);
+  r.tmpB = take(pn * P.nslot * interAB[1] * 4);
   r.pre = P.k == 1 ? r.res : ((P.k - 2) % 2 == 0 ? r.tmpA : r.tmpB);
   r.detv = take(pn * P.G * 4);
   r.den = take(pn * P.G * 4);
@@ -123,14 +124,13 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         const MatPlan& P = mats[chunk[c]];
         BReduce r{};
         r.block0 = vb;
-        r.count = P.nent * P.T;
+        r.count = P.nslot * P.T;
         r.T = P.T;
         r.res_off = (int64_t)reg[c].res;
         r.mat = chunk[c];
-        r.n = P.n;
         r.pn = P.pn;
         r.pc = P.d_pc;
-        r.rowdest = P.d_rowdest;
+        r.slot_src = P.d_slot_src;
         d.push_back(r);
         vb += (r.count + 255) / 256;
       }
@@ -161,17 +161,17 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         e.block0 = vb;
         e.in_off = (int64_t)in_off;
         e.out_off = (int64_t)out_off;
-        e.B = (int64_t)P.pn * P.nent;
+        e.B = (int64_t)P.pn * P.nslot;
         e.outer = outer;
         e.inner = inner;
-        e.nent = P.nent;
+        e.nent = P.nslot;
         e.tw_stride = P.tw_stride;
         e.m = P.m[v];
         e.Nv = P.N[v];
         e.JC = expand_outputs_per_thread(P.N[v], inner, P.m[v]);
         e.tw = P.d_tw + P.tw_off[v];
         e.pc = P.d_pc;
-        e.zero = P.d_zero;
+        e.zero = P.d_slot_zero;
         d.push_back(e);
         vb += (e.B * outer * (expand_jrange(e.Nv, e.m) / e.JC) * inner + 255) / 256;
       }
@@ -212,6 +212,8 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         e.tw0 = P.d_tw + P.tw_off[0];
         e.pc = P.d_pc;
         e.zero = P.d_zero;
+        e.slot = P.d_entry_slot;
+        e.nslot = P.nslot;
         d.push_back(e);
         vb += (int64_t)P.pn * e.rtiles * e.jtiles;
         lds = std::max(lds, fused_tile_words(P.n, P.det_lanes, P.m[0], P.fuse_Q) * 4);

@@ -11,7 +11,7 @@ namespace pd {
 
 // Arguments of the fused evaluation + elimination launch (det_impl.h, det_fused_kernel).
 struct FusedDetArgs {
-  const uint32_t* pre;   // [pn][n*n][m0][R]
+  const uint32_t* pre;   // [pn][nslot][m0][R]
   uint32_t* detv;        // [pn][N0 * R] numerators of the determinants
   uint32_t* denv;        // [pn][N0 * R] denominators
   int64_t R;             // grid points of the other variables
@@ -21,6 +21,8 @@ struct FusedDetArgs {
   int64_t tw_stride;
   const PrimeConst* pcs;
   const uint8_t* zero;   // [n*n] zero-entry flags or null
+  const int32_t* slot;   // [n*n] pre-tensor slot of each entry (elimination order)
+  int64_t nslot;         // slots per prime in the pre-tensor
   int pn;
   bool fixup;            // repair launch: recompute only the points with den = 0
 };

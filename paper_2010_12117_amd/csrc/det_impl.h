@@ -217,16 +217,18 @@ __global__ __launch_bounds__(kDetBlock) void det_kernel(const uint32_t* __restri
   }
 }
 
-// Stages columns r0 .. r0+Q-1 of the pre-tensor pre[n*n][m0][R] (one prime) in LDS as
+// Stages columns r0 .. r0+Q-1 of the pre-tensor pre[nslot][m0][R] (one prime) in LDS as
 // tile[m][q][i * NCP + col] with NCP >= n columns per row (the columns past n-1 hold zeros,
 // so that every lane of a lane group reads the same offsets) and row stride
 // NEP = n*NCP | 1 (odd, so lanes reading different q hit different banks, and the entry
-// offset is an immediate). Zero entries and points past R are stored as zeros without
+// offset is an immediate). Entry e is read from pre-tensor slot slot[e] (entries with equal
+// coefficients share a slot). Zero entries and points past R are stored as zeros without
 // reading memory.
 template <int N, int NCP>
 __device__ __forceinline__ void fill_tile(uint32_t* tile, const uint32_t* __restrict__ src,
                                           int64_t R, int m0, int Q, int64_t r0,
-                                          const uint8_t* __restrict__ zero) {
+                                          const uint8_t* __restrict__ zero,
+                                          const int32_t* __restrict__ slot) {
   constexpr int NEC = N * NCP;
   constexpr int NEP = NEC | 1;
   // Q is a power of two: q = idx mod Q by mask, the padded entry index ec = idx / Q by shift;
@@ -240,7 +242,7 @@ __device__ __forceinline__ void fill_tile(uint32_t* tile, const uint32_t* __rest
     const bool live = col < N && !(zero && zero[e]) && r0 + q < R;
     uint32_t* d = tile + q * NEP + ec;
     if (live) {
-      const uint32_t* s = src + (int64_t)e * m0 * R + r0 + q;
+      const uint32_t* s = src + (int64_t)slot[e] * m0 * R + r0 + q;
       for (int m = 0; m < m0; ++m) d[m * Q * NEP] = s[(int64_t)m * R];
     } else {
       for (int m = 0; m < m0; ++m) d[m * Q * NEP] = 0u;
@@ -269,8 +271,8 @@ __device__ __forceinline__ bool block_needs_fixup(const uint32_t* __restrict__ d
 
 // Fused form: the last evaluation axis (the first variable, whose grid index j0 is the
 // slowest) runs inside the elimination kernel, so the full evaluation tensor never exists.
-// pre[pn][n*n][m0][R] holds every entry already evaluated along the other variables (R
-// points) with its m0 coefficients in the first variable. A block stages the columns
+// pre[pn][nslot][m0][R] holds every evaluated entry (slot) already evaluated along the other
+// variables (R points) with its m0 coefficients in the first variable. A block stages the columns
 // r0 .. r0+Q-1 in LDS (fill_tile) and then, for S values of j0, each lane group rebuilds its
 // matrix at the point (j0, r0 + q) as sum_m x_m w0^{m j0} (the evaluation of Section 2 along
 // x1) and eliminates it with row exchanges. Point index = j0 R + r.
@@ -286,8 +288,8 @@ __device__ __forceinline__ void det_fused_body(
     uint32_t* tile, const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv,
     uint32_t* __restrict__ denv, int64_t R,
     int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, int prime, int64_t bx,
-    bool fixup) {
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
+    const int32_t* __restrict__ entry_slot, int64_t nslot, int prime, int64_t bx, bool fixup) {
   constexpr int C = (N + GL - 1) / GL;
   constexpr int NE = N * N;
   constexpr int NCP = C * GL;  // tile columns per row, padded for the last lane slot
@@ -296,10 +298,10 @@ __device__ __forceinline__ void det_fused_body(
   const int64_t rtiles = (R + Q - 1) / Q;
   const int64_t r0 = (bx % rtiles) * Q;
   const int jbase = (int)(bx / rtiles) * S;
-  const uint32_t* src = pre + (int64_t)prime * NE * m0 * R;
+  const uint32_t* src = pre + (int64_t)prime * nslot * m0 * R;
   const int NJ = PAIR ? N0 / 2 : N0;
   if (fixup && !block_needs_fixup(denv, R, N0, NJ, Q, S, r0, jbase, prime)) return;
-  fill_tile<N, NCP>(tile, src, R, m0, Q, r0, zero);
+  fill_tile<N, NCP>(tile, src, R, m0, Q, r0, zero, entry_slot);
   // Structurally zero entries as a wave-uniform bit mask (one lane per matrix only): the
   // paired evaluation branches around them (scalar branches; their registers are set to 0).
   uint64_t zm[(NE + 63) / 64];
@@ -427,10 +429,11 @@ __global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_w
 void det_fused_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
     int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, bool fixup) {
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
+    const int32_t* __restrict__ slot, int64_t nslot, bool fixup) {
   extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
-  det_fused_body<N, GL, false>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs,
-                               zero, blockIdx.y, blockIdx.x, fixup);
+  det_fused_body<N, GL, false>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
+                               slot, nslot, blockIdx.y, blockIdx.x, fixup);
 }
 
 template <int N, int GL>
@@ -438,10 +441,11 @@ __global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_w
 void det_fused_pair_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
     int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, bool fixup) {
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
+    const int32_t* __restrict__ slot, int64_t nslot, bool fixup) {
   extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
-  det_fused_body<N, GL, true>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs,
-                              zero, blockIdx.y, blockIdx.x, fixup);
+  det_fused_body<N, GL, true>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
+                               slot, nslot, blockIdx.y, blockIdx.x, fixup);
 }
 
 // Batched form: blocks walk the virtual blocks of every matrix of this order in the launch;
@@ -460,8 +464,8 @@ __device__ __forceinline__ void det_fused_batch_body(uint32_t* tile, const BDet*
   const int prime = (int)(local / per_prime);
   det_fused_body<N, GL, PAIR>(tile, (const uint32_t*)(ws + d.pre_off),
                               (uint32_t*)(ws + d.detv_off), (uint32_t*)(ws + d.den_off), d.R,
-                              d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride, d.pc, d.zero, prime,
-                              local - (int64_t)prime * per_prime, fixup);
+                              d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride, d.pc, d.zero, d.slot,
+                              d.nslot, prime, local - (int64_t)prime * per_prime, fixup);
 }
 
 template <int N, int GL>
@@ -576,8 +580,8 @@ __device__ __forceinline__ void det_ll_body(
     uint32_t* tile, const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv,
     uint32_t* __restrict__ denv, int64_t R, int N0, int m0, int Q, int S,
     const uint32_t* __restrict__ tw0, int64_t tw_stride, const PrimeConst* __restrict__ pcs,
-    const uint8_t* __restrict__ zero, int prime, int64_t bx) {
-  constexpr int NE = N * N;
+    const uint8_t* __restrict__ zero, const int32_t* __restrict__ slot, int64_t nslot, int prime,
+    int64_t bx) {
   const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
   // The exchanging kernel's tiles (Q points, S values of j0 in [0, N0/2) with their partners
   // j0 + N0/2 when paired) cover the same points as these: S' = 2 S values of j0 in [0, N0).
@@ -585,7 +589,7 @@ __device__ __forceinline__ void det_ll_body(
   const int64_t rtiles = (R + Q - 1) / Q;
   const int64_t r0 = (bx % rtiles) * Q;
   const int jbase = (int)(bx / rtiles) * S;
-  fill_tile<N, N>(tile, pre + (int64_t)prime * NE * m0 * R, R, m0, Q, r0, zero);
+  fill_tile<N, N>(tile, pre + (int64_t)prime * nslot * m0 * R, R, m0, Q, r0, zero, slot);
   __syncthreads();
 
   const int q = (int)(threadIdx.x % Q);
@@ -630,10 +634,11 @@ template <int N>
 __global__ __launch_bounds__(kDetBlock) void det_ll_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
     int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero) {
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
+    const int32_t* __restrict__ slot, int64_t nslot) {
   extern __shared__ uint32_t tile[];
-  det_ll_body<N>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero, blockIdx.y,
-                 blockIdx.x);
+  det_ll_body<N>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero, slot, nslot,
+                 blockIdx.y, blockIdx.x);
 }
 
 template <int N>
@@ -648,7 +653,7 @@ __global__ __launch_bounds__(kDetBlock) void det_ll_batch_kernel(
   const int prime = (int)(local / per_prime);
   det_ll_body<N>(tile, (const uint32_t*)(ws + d.pre_off), (uint32_t*)(ws + d.detv_off),
                  (uint32_t*)(ws + d.den_off), d.R, d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride,
-                 d.pc, d.zero, prime, local - (int64_t)prime * per_prime);
+                 d.pc, d.zero, d.slot, d.nslot, prime, local - (int64_t)prime * per_prime);
 }
 
 template <int N, int GL>
@@ -684,7 +689,7 @@ hipError_t det_ll_launch(const FusedDetArgs& f, hipStream_t st) {
   const size_t lds = fused_tile_words(N, 1, f.m0, f.Q) * sizeof(uint32_t);
   hipLaunchKernelGGL((det_ll_kernel<N>), dim3((unsigned)(rtiles * jtiles), (unsigned)f.pn),
                      dim3(kDetBlock), lds, st, f.pre, f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S,
-                     f.tw0, f.tw_stride, f.pcs, f.zero);
+                     f.tw0, f.tw_stride, f.pcs, f.zero, f.slot, f.nslot);
   return hipGetLastError();
 }
 
@@ -707,11 +712,11 @@ hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st) {
   if (fused_paired(f.m0))
     hipLaunchKernelGGL((det_fused_pair_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre,
                        f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs,
-                       f.zero, f.fixup);
+                       f.zero, f.slot, f.nslot, f.fixup);
   else
     hipLaunchKernelGGL((det_fused_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre, f.detv,
                        f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs, f.zero,
-                       f.fixup);
+                       f.slot, f.nslot, f.fixup);
   return hipGetLastError();
 }
 

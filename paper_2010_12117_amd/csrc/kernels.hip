@@ -33,17 +33,16 @@ inline unsigned persistent_grid(int64_t vblocks) {
 // ------------------------------------------------------------------------------------
 // S1: int64 coefficient -> representative of (c mod p) for every prime.
 // |c| = hi 2^32 + lo with hi <= 2^31, so c~ = mm(hi, R^3) + mm(lo, R^2), negated for c < 0.
-// Entries are written in elimination row order: input row r goes to row rowdest[r].
+// The residues are laid out by slot: slot u holds input entry slot_src[u] (the entries in
+// elimination row order, or only the distinct nonzero ones).
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ void reduce_body(const int64_t* __restrict__ in,
                                             uint32_t* __restrict__ out, int64_t i, int64_t count,
-                                            int pn, int n, int64_t T,
-                                            const int32_t* __restrict__ rowdest,
+                                            int pn, int64_t T,
+                                            const int32_t* __restrict__ slot_src,
                                             const PrimeConst* __restrict__ pcs) {
-  const int64_t e = i / T;
-  const int row = (int)(e / n), col = (int)(e - (int64_t)row * n);
-  const int64_t dst = ((int64_t)rowdest[row] * n + col) * T + (i - e * T);
-  const int64_t c = in[i];
+  const int64_t u = i / T;
+  const int64_t c = in[(int64_t)slot_src[u] * T + (i - u * T)];
   const bool neg = c < 0;
   const uint64_t a = neg ? (uint64_t)(-(c + 1)) + 1u : (uint64_t)c;
   const uint32_t hi = (uint32_t)(a >> 32), lo = (uint32_t)a;
@@ -51,17 +50,17 @@ __device__ __forceinline__ void reduce_body(const int64_t* __restrict__ in,
     const PrimeConst P = pcs[q];
     uint32_t r = addm(mm(hi, P.r3, P.p, P.pinv), mm(lo, P.r2, P.p, P.pinv), P.p);
     if (neg) r = negm(r, P.p);
-    out[(int64_t)q * count + dst] = r;
+    out[(int64_t)q * count + i] = r;
   }
 }
 
 __global__ __launch_bounds__(kBlock) void reduce_kernel(const int64_t* __restrict__ in,
                                                         uint32_t* __restrict__ out,
-                                                        int64_t count, int pn, int n, int64_t T,
-                                                        const int32_t* __restrict__ rowdest,
+                                                        int64_t count, int pn, int64_t T,
+                                                        const int32_t* __restrict__ slot_src,
                                                         const PrimeConst* __restrict__ pcs) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < count) reduce_body(in, out, i, count, pn, n, T, rowdest, pcs);
+  if (i < count) reduce_body(in, out, i, count, pn, T, slot_src, pcs);
 }
 
 __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
@@ -72,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
     const int64_t i = (vb - d.block0) * kBlock + threadIdx.x;
     if (i < d.count) {
       reduce_body(coeffs + coeff_offsets[d.mat], (uint32_t*)(ws + d.res_off), i, d.count, d.pn,
-                  d.n, d.T, d.rowdest, d.pc);
+                  d.T, d.slot_src, d.pc);
     }
   }
 }
@@ -82,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
 //   in  [B][outer][m][inner]   (coefficients of x_v^e, e < m, other axes as given)
 //   out [B][outer][Nv][inner]  out[j] = sum_e in[e] w_v^{e j}
 // the values at the Nv-th roots of unity (the DFT over Z/pZ of Section 2, restricted to the
-// m nonzero leading coefficients of the zero-padded line). b = prime * nent + entry.
+// m nonzero leading coefficients of the zero-padded line). b = prime * nent + slot.
 // With m >= 2 the outputs come in pairs: since w^{Nv/2} = -1, out[j] = E + O and
 // out[j + Nv/2] = E - O, with E the even terms and O the odd terms at j, so a thread takes
 // j in [0, Nv/2) and half the products. A thread computes JC consecutive j of one line;
@@ -199,22 +198,24 @@ __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __r
 }
 
 // ------------------------------------------------------------------------------------
-// S3 (end): det = num / den at every point. A thread takes kFinalPoints points of one prime,
-// chunks apart (so that a wave's loads and stores are contiguous), and inverts their
-// denominators together (Montgomery's simultaneous inversion: prefix products, one Fermat
-// inverse, then back-substitution), which costs one exponentiation per kFinalPoints points
-// instead of one per point. Every den is nonzero.
+// S3 (end): det = num / den at every point, written to quot (which may be detv itself). A
+// thread takes kFinalPoints points of one prime, chunks apart (so that a wave's loads and
+// stores are contiguous), and inverts their denominators together (Montgomery's simultaneous
+// inversion: prefix products, one Fermat inverse, then back-substitution), which costs one
+// exponentiation per kFinalPoints points instead of one per point. Every den is nonzero.
 // ------------------------------------------------------------------------------------
 constexpr int kFinalPoints = 8;
 
-__device__ __forceinline__ void finalize_body(uint32_t* __restrict__ detv,
-                                              const uint32_t* __restrict__ denv, int64_t t,
-                                              int64_t G, const PrimeConst* __restrict__ pcs) {
+__device__ __forceinline__ void finalize_body(const uint32_t* detv,
+                                              const uint32_t* __restrict__ denv, uint32_t* quot,
+                                              int64_t t, int64_t G,
+                                              const PrimeConst* __restrict__ pcs) {
   const int64_t chunks = (G + kFinalPoints - 1) / kFinalPoints;
   const int prime = (int)(t / chunks);
   const int64_t c = t - (int64_t)prime * chunks;  // points c, c + chunks, c + 2 chunks, ...
   const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv, one = pcs[prime].r1;
-  uint32_t* num = detv + (int64_t)prime * G + c;
+  const uint32_t* num = detv + (int64_t)prime * G + c;
+  uint32_t* q = quot + (int64_t)prime * G + c;
   const uint32_t* den = denv + (int64_t)prime * G + c;
   uint32_t d[kFinalPoints], pre[kFinalPoints];
   uint32_t acc = one;
@@ -229,16 +230,17 @@ __device__ __forceinline__ void finalize_body(uint32_t* __restrict__ detv,
   for (int i = kFinalPoints - 1; i >= 0; --i) {
     const uint32_t di = mm(inv, pre[i], p, pinv);  // 1 / d[i]
     inv = mm(inv, d[i], p, pinv);                   // 1 / (d[0] .. d[i-1])
-    if (c + i * chunks < G) num[i * chunks] = mm(num[i * chunks], di, p, pinv);
+    if (c + i * chunks < G) q[i * chunks] = mm(num[i * chunks], di, p, pinv);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void finalize_kernel(uint32_t* __restrict__ detv,
+__global__ __launch_bounds__(kBlock) void finalize_kernel(const uint32_t* detv,
                                                           const uint32_t* __restrict__ denv,
-                                                          int64_t G, int pn,
+                                                          uint32_t* quot, int64_t G, int pn,
                                                           const PrimeConst* __restrict__ pcs) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t < (int64_t)pn * ((G + kFinalPoints - 1) / kFinalPoints)) finalize_body(detv, denv, t, G, pcs);
+  if (t < (int64_t)pn * ((G + kFinalPoints - 1) / kFinalPoints))
+    finalize_body(detv, denv, quot, t, G, pcs);
 }
 
 __global__ __launch_bounds__(kBlock) void finalize_batch_kernel(const BFinal* __restrict__ desc,
@@ -248,7 +250,9 @@ __global__ __launch_bounds__(kBlock) void finalize_batch_kernel(const BFinal* __
     const BFinal& d = desc[find_desc(desc, ndesc, vb)];
     const int64_t t = (vb - d.block0) * kBlock + threadIdx.x;
     if (t < (int64_t)d.pn * ((d.G + kFinalPoints - 1) / kFinalPoints)) {
-      finalize_body((uint32_t*)(ws + d.detv_off), (const uint32_t*)(ws + d.den_off), t, d.G, d.pc);
+      // in place: the batched interpolation reads the determinants from detv
+      finalize_body((uint32_t*)(ws + d.detv_off), (const uint32_t*)(ws + d.den_off),
+                    (uint32_t*)(ws + d.detv_off), t, d.G, d.pc);
     }
   }
 }
@@ -263,9 +267,9 @@ __global__ __launch_bounds__(kBlock) void finalize_batch_kernel(const BFinal* __
 //
 // With `den` set (the first pass, over the points' numerators and denominators), the load
 // also takes the division of the finalize step: each thread inverts the denominators of
-// kFuseBatch points with one exponentiation (simultaneous inversion), puts num / den in the
-// tile and writes it back over the numerator, so the workspace holds det mod p per point
-// as after a separate finalize launch.
+// kFuseBatch points with one exponentiation (simultaneous inversion) and puts num / den in the
+// tile. The numerators and denominators are left as they are (every stage reads only earlier
+// stages' outputs, so a stage can be run again).
 constexpr int kFuseBatch = 8;
 
 __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __restrict__ in,
@@ -273,8 +277,7 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
                                           int64_t outer, int Nv, int logN, int64_t inner, int Dv1,
                                           int W, const uint32_t* __restrict__ itw,
                                           int64_t tw_stride, const PrimeConst* __restrict__ pcs,
-                                          const uint32_t* __restrict__ den = nullptr,
-                                          uint32_t* quot = nullptr) {
+                                          const uint32_t* __restrict__ den = nullptr) {
   const int64_t lines = outer * inner;
   const int64_t tiles_per_prime = (lines + W - 1) / W;
   const int prime = (int)(block / tiles_per_prime);
@@ -309,9 +312,7 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
     }
   } else {
     const uint32_t one = pcs[prime].r1;
-    const int64_t poff = (int64_t)prime * outer * Nv * inner;
-    const uint32_t* dsrc = den + poff;
-    uint32_t* qdst = quot + poff;
+    const uint32_t* dsrc = den + (int64_t)prime * outer * Nv * inner;
     for (int base = threadIdx.x; base < total; base += kFuseBatch * kBlock) {
       uint32_t v[kFuseBatch], d[kFuseBatch], pre[kFuseBatch];
       int64_t gi[kFuseBatch];
@@ -342,9 +343,7 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
       for (int i = kFuseBatch - 1; i >= 0; --i) {
         const uint32_t di = mm(inv, pre[i], p, pinv);  // 1 / d[i]
         inv = mm(inv, d[i], p, pinv);                   // 1 / (d[0] .. d[i-1])
-        const uint32_t qv = mm(v[i], di, p, pinv);
-        if (gi[i] >= 0) qdst[gi[i]] = qv;
-        if (ti[i] >= 0) tile[ti[i]] = qv;
+        if (ti[i] >= 0) tile[ti[i]] = mm(v[i], di, p, pinv);
       }
     }
   }
@@ -407,10 +406,9 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
 __global__ __launch_bounds__(kBlock) void intt_kernel(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t outer, int Nv, int logN,
     int64_t inner, int Dv1, int W, const uint32_t* __restrict__ itw, int64_t tw_stride,
-    const PrimeConst* __restrict__ pcs, const uint32_t* __restrict__ den, uint32_t* quot) {
+    const PrimeConst* __restrict__ pcs, const uint32_t* __restrict__ den) {
   extern __shared__ uint32_t tile[];  // [Nv][W]
-  intt_body(tile, in, out, blockIdx.x, outer, Nv, logN, inner, Dv1, W, itw, tw_stride, pcs, den,
-            quot);
+  intt_body(tile, in, out, blockIdx.x, outer, Nv, logN, inner, Dv1, W, itw, tw_stride, pcs, den);
 }
 
 __global__ __launch_bounds__(kBlock) void intt_batch_kernel(const BIntt* __restrict__ desc,
@@ -558,19 +556,20 @@ __global__ __launch_bounds__(kBlock) void garner_batch_kernel(
 template <int M>
 hipError_t launch_expand_m(const MatPlan& P, const uint32_t* in, uint32_t* out, int64_t outer,
                            int v, int64_t inner, hipStream_t st) {
-  const int64_t B = (int64_t)P.pn * P.nent;
+  const int64_t B = (int64_t)P.pn * P.nslot;
+  if (B == 0) return hipSuccess;  // every entry is zero
   const int JC = expand_outputs_per_thread(P.N[v], inner, P.m[v]);
   const int64_t work = B * outer * (expand_jrange(P.N[v], P.m[v]) / JC) * inner;
   // the full evaluation tensor (last pass of the unfused path) is read without zero flags
   const bool write_zero = v == 0;
   if (inner >= 64)
     hipLaunchKernelGGL((expand_kernel<M, true>), dim3(blocks_for(work)), dim3(kBlock), 0, st, in,
-                       out, B, outer, P.m[v], P.N[v], JC, inner, P.nent, P.d_tw + P.tw_off[v],
-                       P.tw_stride, P.d_pc, P.d_zero, write_zero);
+                       out, B, outer, P.m[v], P.N[v], JC, inner, P.nslot, P.d_tw + P.tw_off[v],
+                       P.tw_stride, P.d_pc, P.d_slot_zero, write_zero);
   else
     hipLaunchKernelGGL((expand_kernel<M, false>), dim3(blocks_for(work)), dim3(kBlock), 0, st, in,
-                       out, B, outer, P.m[v], P.N[v], JC, inner, P.nent, P.d_tw + P.tw_off[v],
-                       P.tw_stride, P.d_pc, P.d_zero, write_zero);
+                       out, B, outer, P.m[v], P.N[v], JC, inner, P.nslot, P.d_tw + P.tw_off[v],
+                       P.tw_stride, P.d_pc, P.d_slot_zero, write_zero);
   return hipGetLastError();
 }
 
@@ -611,6 +610,8 @@ hipError_t launch_det_ng(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hi
   f.tw_stride = P.tw_stride;
   f.pcs = P.d_pc;
   f.zero = P.d_zero;
+  f.slot = P.d_entry_slot;
+  f.nslot = P.nslot;
   f.pn = P.pn;
   f.fixup = false;
   if constexpr (N <= kLLMaxN) {
@@ -728,9 +729,10 @@ int intt_lines_per_block(int64_t lines, int Nv, int pn) {
 }
 
 hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st) {
-  const int64_t count = P.nent * P.T;
+  const int64_t count = P.nslot * P.T;
+  if (count == 0) return hipSuccess;  // every entry is zero
   hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(count)), dim3(kBlock), 0, st, coeffs,
-                     (uint32_t*)(ws + P.off_res), count, P.pn, P.n, P.T, P.d_rowdest, P.d_pc);
+                     (uint32_t*)(ws + P.off_res), count, P.pn, P.T, P.d_slot_src, P.d_pc);
   return hipGetLastError();
 }
 
@@ -766,8 +768,8 @@ hipError_t run_finalize(const MatPlan& P, uint8_t* ws, hipStream_t st) {
   // with variables the first interpolation pass divides as it loads (intt_body)
   if (P.k > 0) return hipSuccess;
   hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(finalize_threads(P.G, P.pn))), dim3(kBlock),
-                     0, st, (uint32_t*)(ws + P.off_detv), (const uint32_t*)(ws + P.off_den), P.G,
-                     P.pn, P.d_pc);
+                     0, st, (const uint32_t*)(ws + P.off_detv), (const uint32_t*)(ws + P.off_den),
+                     (uint32_t*)(ws + P.off_coef), P.G, P.pn, P.d_pc);
   return hipGetLastError();
 }
 
@@ -794,10 +796,9 @@ hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
     const size_t lds = (size_t)(Nv * W + Nv / 2) * sizeof(uint32_t);
     // the first pass also divides each point's numerator by its denominator
     const uint32_t* den = v == 0 ? (const uint32_t*)(ws + P.off_den) : nullptr;
-    uint32_t* quot = v == 0 ? (uint32_t*)(ws + P.off_detv) : nullptr;
     hipLaunchKernelGGL(intt_kernel, dim3((unsigned)(tiles * P.pn)), dim3(kBlock), lds, st, in, out,
                        outer, Nv, logN, inner, P.D[v] + 1, W, P.d_itw + P.tw_off[v], P.tw_stride,
-                       P.d_pc, den, quot);
+                       P.d_pc, den);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     in = out;

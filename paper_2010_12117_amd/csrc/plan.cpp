@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 
 namespace pd {
 
@@ -270,6 +271,51 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     P.entry_zero.swap(z);
   }
 
+  // Slots: the distinct nonzero entries when the coefficients are known (see plan.h); the
+  // layout below falls back to every entry when the elimination cannot evaluate the first
+  // variable itself (the unfused path reads the full evaluation tensor by entry).
+  auto identity_slots = [&]() {
+    P.nslot = P.nent;
+    P.slot_src.resize(P.nent);
+    P.entry_slot.resize(P.nent);
+    for (int i = 0; i < s.n; ++i) {
+      for (int j = 0; j < s.n; ++j) {
+        P.slot_src[i * s.n + j] = P.row_order[i] * s.n + j;
+        P.entry_slot[i * s.n + j] = i * s.n + j;
+      }
+    }
+  };
+  identity_slots();
+  if (host_coeffs && s.k >= 1 && !(flags & 1u)) {
+    std::vector<int32_t> src, slot(P.nent, -1);
+    std::unordered_map<uint64_t, std::vector<int32_t>> by_hash;  // box hash -> slots
+    for (int64_t e = 0; e < P.nent; ++e) {
+      if (P.entry_zero[e]) continue;
+      const int64_t in_e = (int64_t)P.row_order[e / s.n] * s.n + e % s.n;
+      const int64_t* box = host_coeffs + in_e * P.T;
+      uint64_t h = 1469598103934665603ull;  // FNV-1a over the box's bytes
+      const unsigned char* bytes = (const unsigned char*)box;
+      for (size_t b = 0; b < sizeof(int64_t) * (size_t)P.T; ++b) h = (h ^ bytes[b]) * 1099511628211ull;
+      auto& bucket = by_hash[h];
+      int found = -1;
+      for (int32_t u : bucket) {
+        if (std::memcmp(host_coeffs + (int64_t)src[u] * P.T, box, sizeof(int64_t) * P.T) == 0) {
+          found = u;
+          break;
+        }
+      }
+      if (found < 0) {
+        found = (int)src.size();
+        src.push_back((int32_t)in_e);
+        bucket.push_back(found);
+      }
+      slot[e] = found;
+    }
+    P.nslot = (int64_t)src.size();
+    P.slot_src.swap(src);
+    P.entry_slot.swap(slot);
+  }
+
   P.pc.resize(P.pn);
   for (int i = 0; i < P.pn; ++i) {
     const uint32_t p = P.primes[i];
@@ -308,18 +354,19 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     off = align256(off + bytes);
     return o;
   };
-  P.off_res = take(pg * P.nent * P.T * 4);
-  // forward passes run over the last variable first; the output of pass v has shape
-  // [pn*nent][prod_{u<v} m_u][prod_{u>=v} N_u]
-  size_t inter = 0;
-  for (int v = s.k - 1; v >= 1; --v) {
+  P.off_res = take(pg * std::max<int64_t>(P.nslot, 1) * P.T * 4);
+  // forward passes run over the last variable first, writing tmpA, tmpB, tmpA, ... in turn;
+  // the output of the pass over variable v has shape [pn*nent][prod_{u<v} m_u][prod_{u>=v} N_u]
+  size_t interAB[2] = {0, 0};
+  for (int v = s.k - 1; v >= 1; --v) {  // the pass over variable 0 writes off_eval or is fused
     int64_t sz = 1;
     for (int u = 0; u < v; ++u) sz *= P.m[u];
     for (int u = v; u < s.k; ++u) sz *= P.N[u];
-    inter = std::max(inter, (size_t)sz);
+    const int which = (s.k - 1 - v) % 2;
+    interAB[which] = std::max(interAB[which], (size_t)sz);
   }
-  P.off_tmpA = take(pg * P.nent * inter * 4);
-  P.off_tmpB = take(pg * P.nent * inter * 4);
+  P.off_tmpA = take(pg * P.nslot * interAB[0] * 4);
+  P.off_tmpB = take(pg * P.nslot * interAB[1] * 4);
   // Fused evaluation of the first variable inside the elimination kernel: a block stages
   // Q points of every entry (m0 coefficients each) in LDS, at most kFuseLds bytes, and
   // handles S values of the first variable's grid index.
@@ -334,6 +381,14 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
                      fused_tile_words(P.n, P.det_lanes, P.m[0], Q) * 4 > kFuseLds)) Q >>= 1;
     if (fused_tile_words(P.n, P.det_lanes, P.m[0], Q) * 4 > kFuseLds) {
       P.fused = false;  // the tile does not fit: evaluate in full, then eliminate
+      if (P.nslot != P.nent) {  // the full evaluation tensor is indexed by entry
+        identity_slots();
+        P.off_res = 0;
+        off = 0;
+        P.off_res = take(pg * P.nslot * P.T * 4);
+        P.off_tmpA = take(pg * P.nslot * interAB[0] * 4);
+        P.off_tmpB = take(pg * P.nslot * interAB[1] * 4);
+      }
     } else {
       const int J = per_block / Q;
       const int64_t base_blocks = (int64_t)pg * ((R + Q - 1) / Q);
@@ -369,7 +424,7 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   }
   P.off_iA = take(pg * iinter * 4);
   P.off_iB = take(pg * iinter * 4);
-  P.off_coef = s.k == 0 ? P.off_detv : take((size_t)P.pn * P.C * 4);
+  P.off_coef = take((size_t)P.pn * P.C * 4);
   return std::max<size_t>(off, 256);
   };
   P.prime_group = P.pn;
@@ -399,15 +454,9 @@ MatPlan prime_range_plan(const MatPlan& P, int b, int e) {
   for (int v = 0; v < P.k; ++v) {
     R.tw_off[v] = P.tw_off[v] + (int64_t)b * P.tw_stride;
   }
-  if (P.k == 0) {
-    // an integer matrix: the determinant of prime i is its coefficient residue, at slot i of
-    // regions that hold all pn primes
-    R.off_detv = P.off_detv + (size_t)b * 4;
-    R.off_den = P.off_den + (size_t)b * 4;
-    R.off_coef = R.off_detv;
-  } else {
-    R.off_coef = P.off_coef + (size_t)b * P.C * 4;
-  }
+  // the per-prime regions hold the group's primes from slot 0; the coefficient region holds
+  // all pn primes (for an integer matrix, C = 1: the determinant residue of each prime)
+  R.off_coef = P.off_coef + (size_t)b * P.C * 4;
   return R;
 }
 
@@ -426,7 +475,7 @@ int upload_tables(Plan* plan) {
   std::vector<size_t> offs;
   size_t total = 0;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-  struct Sizes { size_t pc, tw, gw, gc, ml, zero, rd; };
+  struct Sizes { size_t pc, tw, gw, gc, ml, zero, ss, es; };
   std::vector<Sizes> sz;
   for (auto& P : plan->mats) {
     int64_t stride = 0;
@@ -442,10 +491,11 @@ int upload_tables(Plan* plan) {
     z.gc = al(4 * P.pn);
     z.ml = al(4 * P.L);
     z.zero = P.entry_zero.empty() ? 0 : al(P.nent);
-    z.rd = al(4 * P.n);
+    z.ss = al(4 * std::max<int64_t>(P.nslot, 1));
+    z.es = al(4 * P.nent);
     sz.push_back(z);
     offs.push_back(total);
-    total += z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero + z.rd;
+    total += z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero + z.ss + z.es;
   }
   std::vector<uint8_t> host(std::max<size_t>(total, 256), 0);
   for (size_t idx = 0; idx < plan->mats.size(); ++idx) {
@@ -497,8 +547,9 @@ int upload_tables(Plan* plan) {
     if (z.zero) {
       std::memcpy(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml, P.entry_zero.data(), P.nent);
     }
-    int32_t* rd = (int32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero);
-    for (int i = 0; i < P.n; ++i) rd[P.row_order[i]] = i;
+    uint8_t* ss = base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero;
+    if (P.nslot) std::memcpy(ss, P.slot_src.data(), 4 * P.nslot);
+    std::memcpy(ss + z.ss, P.entry_slot.data(), 4 * P.nent);
   }
   void* d = nullptr;
   hipError_t err = hipMalloc(&d, host.size());
@@ -521,7 +572,10 @@ int upload_tables(Plan* plan) {
     P.d_mlimbs = (const uint32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc);
     P.d_hlimbs = (const uint32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + z.ml);
     P.d_zero = z.zero ? (const uint8_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml) : nullptr;
-    P.d_rowdest = (const int32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero);
+    P.d_slot_src = (const int32_t*)(base + z.pc + 2 * z.tw + z.gw + z.gc + 2 * z.ml + z.zero);
+    P.d_entry_slot = (const int32_t*)((const uint8_t*)P.d_slot_src + z.ss);
+    // the evaluation passes skip zero slots only when slots are entries (no dedup)
+    P.d_slot_zero = P.nslot == P.nent ? P.d_zero : nullptr;
   }
   return 0;
 }

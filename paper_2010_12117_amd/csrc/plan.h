@@ -70,6 +70,14 @@ struct MatPlan {
   std::vector<uint32_t> primes;
   std::vector<PrimeConst> pc;
   std::vector<uint8_t> entry_zero;  // empty when the plan was built without coefficients
+  // Evaluated entries ("slots"): reduce and the evaluation passes run over nslot entries, slot
+  // u holding input entry slot_src[u]; the elimination finds entry e (elimination order) at
+  // slot entry_slot[e] (-1 for a zero entry). With coefficients and the fused evaluation the
+  // slots are the distinct nonzero entries (equal coefficient boxes share one slot: the
+  // replication of entries, e.g. in Sylvester matrices); otherwise every entry in elimination
+  // order.
+  int64_t nslot = 0;
+  std::vector<int32_t> slot_src, entry_slot;
   // Rows in elimination order: row i of the matrix the kernels see is input row
   // row_order[i]. Chosen on the host from the zero pattern so that no pivot is structurally
   // zero; det_sign is the sign of that permutation.
@@ -88,7 +96,9 @@ struct MatPlan {
   const uint32_t* d_mlimbs = nullptr;  // [L] M = p_0..p_{pn-1}
   const uint32_t* d_hlimbs = nullptr;  // [L] (M-1)/2
   const uint8_t* d_zero = nullptr;     // [nent] or null (in elimination row order)
-  const int32_t* d_rowdest = nullptr;  // [n] position of input row i in elimination order
+  const int32_t* d_slot_src = nullptr;    // [nslot] input entry of each slot
+  const int32_t* d_entry_slot = nullptr;  // [nent] slot of each entry (elimination order)
+  const uint8_t* d_slot_zero = nullptr;   // zero flags by slot for the evaluation passes (or null)
 
   // fused first-variable evaluation + elimination (det_fused_kernel)
   bool fused = false;

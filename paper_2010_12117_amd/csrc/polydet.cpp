@@ -9,6 +9,7 @@
 #include <new>
 #include <string>
 
+#include "abi_internal.h"
 #include "batch_plan.h"
 #include "kernels.h"
 #include "plan.h"
@@ -25,6 +26,15 @@ struct StageTimer {
   bool ready = false;
 };
 
+// POLYDET_STAGE_TIMING for batched solves: an event before and after every launch, read back
+// (and added to the stage of the launch's kind) before the next solve records them again.
+struct BatchTimer {
+  std::vector<hipEvent_t> ev;  // [2 * launches]
+  bool pending = false;
+  int64_t solves = 0;
+  double ms[POLYDET_NUM_STAGES] = {0};
+};
+
 // Device state of a batched solve: the descriptor tables and the offset arrays.
 struct BatchState {
   pd::BatchPlan bp;
@@ -32,6 +42,7 @@ struct BatchState {
   int64_t* d_offsets = nullptr;          // [2][count]: coefficient offsets, output offsets
   std::vector<int64_t> h_offsets;        // what d_offsets holds
   bool plain = false;
+  BatchTimer* timer = nullptr;
 };
 
 struct polydet_plan_s {
@@ -92,6 +103,14 @@ polydet_status make_batch(polydet_plan_s* h, uint32_t flags) {
   }
   e = hipMalloc((void**)&B->d_offsets, 2 * sizeof(int64_t) * h->plan.mats.size());
   if (e != hipSuccess) return hip_fail(e, "batch offsets");
+  if (flags & POLYDET_STAGE_TIMING) {
+    B->timer = new (std::nothrow) BatchTimer();
+    if (!B->timer) return fail(POLYDET_ENOMEM, "host allocation failed");
+    B->timer->ev.assign(2 * B->bp.launches.size(), nullptr);
+    for (auto& ev : B->timer->ev) {
+      if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+  }
   return POLYDET_OK;
 }
 
@@ -152,7 +171,7 @@ polydet_status make_plan(const polydet_shape* shapes, int32_t count,
       return bs;
     }
   }
-  if (flags & POLYDET_STAGE_TIMING) {
+  if ((flags & POLYDET_STAGE_TIMING) && !(h->batch && h->batch->timer)) {
     h->timer = new (std::nothrow) StageTimer();
     if (!h->timer) {
       polydet_plan_destroy(h);
@@ -189,6 +208,38 @@ hipError_t harvest(StageTimer* T, int slot) {
   return hipSuccess;
 }
 
+int stage_of(pd::BLaunch::Kind k) {
+  switch (k) {
+    case pd::BLaunch::kReduce: return 0;
+    case pd::BLaunch::kExpand: return 1;
+    case pd::BLaunch::kDet: return 2;
+    case pd::BLaunch::kFinal: return 3;
+    case pd::BLaunch::kIntt: return 4;
+    default: return 5;
+  }
+}
+
+hipError_t harvest_batch(BatchState* B) {
+  BatchTimer* T = B->timer;
+  if (!T || !T->pending) return hipSuccess;
+  const size_t nl = B->bp.launches.size();
+  if (nl == 0) {
+    T->pending = false;
+    T->solves += 1;
+    return hipSuccess;
+  }
+  hipError_t e = hipEventSynchronize(T->ev[2 * nl - 1]);
+  if (e != hipSuccess) return e;
+  for (size_t i = 0; i < nl; ++i) {
+    float ms = 0;
+    if ((e = hipEventElapsedTime(&ms, T->ev[2 * i], T->ev[2 * i + 1])) != hipSuccess) return e;
+    T->ms[stage_of(B->bp.launches[i].kind)] += ms;
+  }
+  T->pending = false;
+  T->solves += 1;
+  return hipSuccess;
+}
+
 // S1-S4 for primes [b, e), prime_group at a time; each group leaves its coefficient residues
 // in the coefficient region.
 polydet_status run_primes(const pd::MatPlan& P, const int64_t* d_coeffs, int b, int e,
@@ -206,6 +257,51 @@ polydet_status run_primes(const pd::MatPlan& P, const int64_t* d_coeffs, int b, 
   return POLYDET_OK;
 }
 
+// One stage of a solve: S1 reduce, S2 evaluate, S3 determinants (numerators and
+// denominators), S3 end (finalize: the division, a launch of its own only without variables),
+// S4 interpolate, S5 reconstruct.
+hipError_t run_stage(const pd::MatPlan& P, int stage, const int64_t* d_coeffs, uint32_t* d_out,
+                     uint8_t* ws, hipStream_t st) {
+  switch (stage) {
+    case 0: return pd::run_reduce(P, d_coeffs, ws, st);
+    case 1: return pd::run_evaluate(P, ws, st);
+    case 2: return pd::run_det(P, ws, st);
+    case 3: return pd::run_finalize(P, ws, st);
+    case 4: return pd::run_interpolate(P, ws, st);
+    default: return pd::run_reconstruct(P, ws, d_out, st);
+  }
+}
+
+const char* const kStageNames[POLYDET_NUM_STAGES] = {"reduce", "evaluate", "determinants",
+                                                     "finalize", "interpolate", "reconstruct"};
+
+// Stages [b, e) of the solve of P (all primes at once), with the plan's stage events if any.
+polydet_status run_stages(const pd::MatPlan& P, int b, int e, const int64_t* d_coeffs,
+                          uint32_t* d_out, uint8_t* ws, hipStream_t st, StageTimer* T) {
+  hipError_t err;
+  hipEvent_t* ev = nullptr;
+  if (T) {
+    const int slot = (int)(T->next++ % StageTimer::kSlots);
+    if ((err = harvest(T, slot)) != hipSuccess) return hip_fail(err, "stage timing");
+    ev = T->ev[slot];
+    T->pending[slot] = true;
+    // stages outside [b, e) read as zero: their two events are recorded back to back
+    for (int s = 0; s <= b; ++s) {
+      if ((err = hipEventRecord(ev[s], st)) != hipSuccess) return hip_fail(err, "stage timing");
+    }
+  }
+  for (int s = b; s < e; ++s) {
+    if ((err = run_stage(P, s, d_coeffs, d_out, ws, st)) != hipSuccess)
+      return hip_fail(err, kStageNames[s]);
+    if (ev && (err = hipEventRecord(ev[s + 1], st)) != hipSuccess)
+      return hip_fail(err, "stage timing");
+  }
+  for (int s = e + 1; ev && s <= POLYDET_NUM_STAGES; ++s) {
+    if ((err = hipEventRecord(ev[s], st)) != hipSuccess) return hip_fail(err, "stage timing");
+  }
+  return POLYDET_OK;
+}
+
 polydet_status run_one(const pd::MatPlan& P, const int64_t* d_coeffs, uint32_t* d_out,
                        uint8_t* ws, hipStream_t st, StageTimer* T) {
   if (P.prime_group < P.pn) {  // capped workspace: S1-S4 by prime groups, then S5
@@ -214,29 +310,7 @@ polydet_status run_one(const pd::MatPlan& P, const int64_t* d_coeffs, uint32_t* 
     hipError_t e = pd::run_reconstruct(P, ws, d_out, st);
     return e == hipSuccess ? POLYDET_OK : hip_fail(e, "reconstruct");
   }
-  hipError_t e;
-  hipEvent_t* ev = nullptr;
-  if (T) {
-    const int slot = (int)(T->next++ % StageTimer::kSlots);
-    if ((e = harvest(T, slot)) != hipSuccess) return hip_fail(e, "stage timing");
-    ev = T->ev[slot];
-    T->pending[slot] = true;
-  }
-  auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
-  if ((e = mark(0)) != hipSuccess) return hip_fail(e, "stage timing");
-  if ((e = pd::run_reduce(P, d_coeffs, ws, st)) != hipSuccess) return hip_fail(e, "reduce");
-  if ((e = mark(1)) != hipSuccess) return hip_fail(e, "stage timing");
-  if ((e = pd::run_evaluate(P, ws, st)) != hipSuccess) return hip_fail(e, "evaluate");
-  if ((e = mark(2)) != hipSuccess) return hip_fail(e, "stage timing");
-  if ((e = pd::run_det(P, ws, st)) != hipSuccess) return hip_fail(e, "determinants");
-  if ((e = mark(3)) != hipSuccess) return hip_fail(e, "stage timing");
-  if ((e = pd::run_finalize(P, ws, st)) != hipSuccess) return hip_fail(e, "finalize");
-  if ((e = mark(4)) != hipSuccess) return hip_fail(e, "stage timing");
-  if ((e = pd::run_interpolate(P, ws, st)) != hipSuccess) return hip_fail(e, "interpolate");
-  if ((e = mark(5)) != hipSuccess) return hip_fail(e, "stage timing");
-  if ((e = pd::run_reconstruct(P, ws, d_out, st)) != hipSuccess) return hip_fail(e, "reconstruct");
-  if ((e = mark(6)) != hipSuccess) return hip_fail(e, "stage timing");
-  return POLYDET_OK;
+  return run_stages(P, 0, POLYDET_NUM_STAGES, d_coeffs, d_out, ws, st, T);
 }
 
 polydet_status check_device(const pd::Plan& plan) {
@@ -252,6 +326,8 @@ polydet_status check_device(const pd::Plan& plan) {
 }
 
 }  // namespace
+
+polydet_status pd::abi_fail(polydet_status st, const std::string& msg) { return fail(st, msg); }
 
 extern "C" {
 
@@ -303,6 +379,8 @@ polydet_status polydet_plan_query(polydet_plan_t plan, int32_t index, polydet_pl
   out->off_eval = P.off_eval;
   out->off_detv = P.off_detv;
   out->off_coef = P.off_coef;
+  out->off_den = P.off_den;
+  out->nslots = P.nslot;
   return POLYDET_OK;
 }
 
@@ -327,6 +405,27 @@ polydet_status polydet_solve(polydet_plan_t plan, const int64_t* d_coeffs, uint3
   polydet_status st = check_device(plan->plan);
   if (st != POLYDET_OK) return st;
   return run_one(P, d_coeffs, d_out, (uint8_t*)d_workspace, (hipStream_t)stream, plan->timer);
+}
+
+polydet_status polydet_solve_stages(polydet_plan_t plan, int32_t stage_begin, int32_t stage_end,
+                                    const int64_t* d_coeffs, uint32_t* d_out, void* d_workspace,
+                                    size_t workspace_bytes, void* stream) {
+  if (!plan) return fail(POLYDET_EINVAL, "NULL plan");
+  if (plan->plan.batch) return fail(POLYDET_EINVAL, "batch plans are solved by polydet_solve_batch");
+  if (stage_begin < 0 || stage_end > POLYDET_NUM_STAGES || stage_begin >= stage_end)
+    return fail(POLYDET_EINVAL, "stages must satisfy 0 <= begin < end <= POLYDET_NUM_STAGES");
+  if (!d_workspace) return fail(POLYDET_EINVAL, "NULL workspace");
+  if (stage_begin == 0 && !d_coeffs) return fail(POLYDET_EINVAL, "NULL coefficients");
+  if (stage_end == POLYDET_NUM_STAGES && !d_out) return fail(POLYDET_EINVAL, "NULL output");
+  const pd::MatPlan& P = plan->plan.mats[0];
+  if (P.prime_group < P.pn)
+    return fail(POLYDET_EINVAL, "a capped plan runs by prime ranges (polydet_solve_primes)");
+  if (workspace_bytes < P.ws_bytes) return fail(POLYDET_EINVAL, "workspace too small");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(POLYDET_EINVAL, "workspace must be 256-byte aligned");
+  polydet_status st = check_device(plan->plan);
+  if (st != POLYDET_OK) return st;
+  return run_stages(P, stage_begin, stage_end, d_coeffs, d_out, (uint8_t*)d_workspace,
+                    (hipStream_t)stream, plan->timer);
 }
 
 static polydet_status check_single(polydet_plan_t plan, void* d_workspace,
@@ -384,9 +483,17 @@ static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
   }
   const int64_t* d_coff = B->d_offsets;
   const int64_t* d_ooff = B->d_offsets + count;
-  for (const pd::BLaunch& L : B->bp.launches) {
+  BatchTimer* T = B->timer;
+  if (T) {
+    hipError_t e = harvest_batch(B);
+    if (e != hipSuccess) return hip_fail(e, "stage timing");
+    T->pending = true;
+  }
+  for (size_t li = 0; li < B->bp.launches.size(); ++li) {
+    const pd::BLaunch& L = B->bp.launches[li];
     const void* desc = B->d_desc + L.desc_off;
     hipError_t e = hipSuccess;
+    if (T && (e = hipEventRecord(T->ev[2 * li], st)) != hipSuccess) return hip_fail(e, "stage timing");
     switch (L.kind) {
       case pd::BLaunch::kReduce:
         e = pd::batch_reduce((const pd::BReduce*)desc, L.ndesc, L.vblocks, d_coeffs, d_coff, ws, st);
@@ -410,6 +517,8 @@ static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
         break;
     }
     if (e != hipSuccess) return hip_fail(e, "batched launch");
+    if (T && (e = hipEventRecord(T->ev[2 * li + 1], st)) != hipSuccess)
+      return hip_fail(e, "stage timing");
   }
   for (int i : B->bp.singles) {
     polydet_status r = run_one(plan->plan.mats[i], d_coeffs + coeff_offsets[i],
@@ -449,6 +558,18 @@ polydet_status polydet_solve_batch(polydet_plan_t plan, const int64_t* d_coeffs,
 polydet_status polydet_stage_times(polydet_plan_t plan, double ms[POLYDET_NUM_STAGES],
                                    int64_t* solves) {
   if (!plan || !ms) return fail(POLYDET_EINVAL, "NULL plan or output");
+  if (plan->batch && plan->batch->timer) {
+    BatchTimer* BT = plan->batch->timer;
+    hipError_t e = harvest_batch(plan->batch);
+    if (e != hipSuccess) return hip_fail(e, "stage timing");
+    for (int s = 0; s < POLYDET_NUM_STAGES; ++s) {
+      ms[s] = BT->ms[s];
+      BT->ms[s] = 0;
+    }
+    if (solves) *solves = BT->solves;
+    BT->solves = 0;
+    return POLYDET_OK;
+  }
   StageTimer* T = plan->timer;
   if (!T) return fail(POLYDET_EINVAL, "the plan was made without POLYDET_STAGE_TIMING");
   for (int slot = 0; slot < StageTimer::kSlots; ++slot) {
@@ -476,6 +597,14 @@ void polydet_plan_destroy(polydet_plan_t plan) {
     delete plan->timer;
   }
   if (plan->batch) {
+    if (plan->batch->timer) {
+      if (plan->batch->timer->pending && !plan->batch->timer->ev.empty())
+        (void)hipEventSynchronize(plan->batch->timer->ev.back());
+      for (auto& ev : plan->batch->timer->ev) {
+        if (ev) (void)hipEventDestroy(ev);
+      }
+      delete plan->batch->timer;
+    }
     if (plan->batch->d_desc) (void)hipFree(plan->batch->d_desc);
     if (plan->batch->d_offsets) (void)hipFree(plan->batch->d_offsets);
     delete plan->batch;

@@ -41,6 +41,23 @@ def gpu_solve(arr, flags=0, use_coeffs=True):
     return res.reshape(box) if box else res.reshape(()), pl, ws
 
 
+def det_regions(pl, ws):
+    """(numerators, denominators) per (prime, point), uint32 [pn][G] (Montgomery form)."""
+    info = pl.info
+    nb = 4 * info["pn"] * info["G"]
+    w = ws.cpu().numpy()
+    num = w[info["off_detv"]:info["off_detv"] + nb].view(np.uint32).reshape(info["pn"], info["G"])
+    den = w[info["off_den"]:info["off_den"] + nb].view(np.uint32).reshape(info["pn"], info["G"])
+    return num, den
+
+
+def assert_same_fractions(pla, wsa, plb, wsb):
+    """Both solves left the same numerator and denominator at every (prime, point)."""
+    na, da = det_regions(pla, wsa)
+    nb, db = det_regions(plb, wsb)
+    assert np.array_equal(na, nb) and np.array_equal(da, db)
+
+
 def oracle_box(arr):
     n, deg = B.shape_of(arr)
     return OD.det_pointwise(arr, PL.det_degree_bound_from_shape(n, deg))
@@ -143,11 +160,7 @@ def test_left_looking_repairs_zero_pivots(n, kind):
     b, plb, wsb = gpu_solve(arr, flags=pdm.DET_EXCHANGE)
     assert pla.info["det_left_looking"] == 1 and plb.info["det_left_looking"] == 0
     assert box_to_dict(a) == box_to_dict(b) == box_to_dict(oracle_box(arr))
-    ia, ib = pla.info, plb.info
-    nb = 4 * ia["pn"] * ia["G"]
-    da = wsa.cpu().numpy()[ia["off_detv"]:ia["off_detv"] + nb]
-    db = wsb.cpu().numpy()[ib["off_detv"]:ib["off_detv"] + nb]
-    assert np.array_equal(da, db)
+    assert_same_fractions(pla, wsa, plb, wsb)
 
 
 @pytest.mark.parametrize("n", list(range(1, 17)))
@@ -229,8 +242,7 @@ def test_stages_against_oracle_steps():
     w = ws.cpu().numpy()
     ev = w[info["off_eval"]:info["off_eval"] + 4 * info["pn"] * n * n * G].view(np.uint32)
     ev = ev.reshape(info["pn"], n * n, G)
-    dv = w[info["off_detv"]:info["off_detv"] + 4 * info["pn"] * G].view(np.uint32)
-    dv = dv.reshape(info["pn"], G)
+    num, den = det_regions(pl, ws)
     cf = w[info["off_coef"]:info["off_coef"] + 4 * info["pn"] * info["ncoeff"]].view(np.uint32)
     cf = cf.reshape(info["pn"], info["ncoeff"])
     M = P.matrix_from_array(arr, n, k)
@@ -247,7 +259,8 @@ def test_stages_against_oracle_steps():
                 for c in range(n):
                     # row r of the eliminated matrix is input row order[r]
                     assert mont_to_plain(ev[q, r * n + c, idx], p) == A[order[r]][c]
-            assert mont_to_plain(dv[q, idx], p) == info["det_sign"] * OM.det_mod(A, p) % p
+            d = mont_to_plain(num[q, idx], p) * pow(mont_to_plain(den[q, idx], p), p - 2, p)
+            assert d % p == info["det_sign"] * OM.det_mod(A, p) % p
         for e in itertools.product(*[range(b) for b in box]):
             ci = node_index(e, box)
             # the interpolation leaves the factor G (and the row-order sign) for the
@@ -269,11 +282,7 @@ def test_fused_matches_unfused_and_stage_values(n, deg, lanes):
     a, pla, wsa = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2))
     b, plb, wsb = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2) | pdm.UNFUSED_EVAL)
     assert box_to_dict(a) == box_to_dict(b)
-    ia, ib = pla.info, plb.info
-    nb = 4 * ia["pn"] * ia["G"]
-    da = wsa.cpu().numpy()[ia["off_detv"]:ia["off_detv"] + nb]
-    db = wsb.cpu().numpy()[ib["off_detv"]:ib["off_detv"] + nb]
-    assert np.array_equal(da, db)
+    assert_same_fractions(pla, wsa, plb, wsb)
 
 
 def test_config2_bit_exact(pool):
@@ -301,3 +310,47 @@ def test_config3b_resultant_closed_form():
             term = P.sub(P.mul(box_to_dict(b), box_to_dict(c)), P.mul(box_to_dict(a), box_to_dict(d)))
             expect = P.mul(expect, term)
     assert box_to_dict(got) == expect
+
+
+def _large_order_cases():
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_large_order_digests as LG
+    return LG
+
+
+@pytest.mark.parametrize("idx", range(7))
+def test_large_orders_term_by_term_evaluation(idx):
+    # orders 25-32 whose first variable has 1 or 5-7 coefficients: the elimination kernels
+    # that evaluate that variable term by term (not in pairs), with 8 and 16 lanes per matrix
+    # and the default mapping, against the oracle's exact determinant (stored digests written
+    # by tests/golden/make_large_order_digests.py from the pointwise oracle)
+    import json
+    LG = _large_order_cases()
+    from make_config4_digests import digest
+    n, deg, seed = LG.CASES[idx]
+    want = json.load(open(LG.OUT))["digests"][LG.case_key(n, deg, seed)]
+    arr = LG.case_matrix(n, deg, seed)
+    assert not (2 <= deg[0] + 1 <= 4)  # not the paired form
+    for flags in (pdm.DET_LANES_LOG2(3), pdm.DET_LANES_LOG2(4), 0):
+        got, pl, _ = gpu_solve(arr, flags=flags | pdm.DET_EXCHANGE)
+        assert pl.info["pn"] >= 15
+        assert digest(got) == want, (n, deg, pl.info["det_lanes"])
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_repeated_entries_are_evaluated_once(lanes):
+    # a block matrix whose entries repeat (and some are zero), solved with one slot per
+    # distinct entry, equals the solve that evaluates every entry (the full evaluation tensor)
+    # and the oracle
+    rng = np.random.default_rng(400 + lanes)
+    base = W.random_matrix(rng, 3, (2, 1, 1), -40, 40, zero_prob=0.2)
+    arr = np.concatenate([np.concatenate([base, base[::-1]], axis=1),
+                          np.concatenate([base[:, ::-1], base], axis=1)], axis=0)
+    arr[0, 5] = arr[4, 1]
+    log2 = {1: 0, 2: 1, 4: 2}[lanes]
+    got, pl, _ = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2))
+    ref, plu, _ = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2) | pdm.UNFUSED_EVAL)
+    assert pl.info["nslots"] < 18 and plu.info["nslots"] == 36
+    assert box_to_dict(got) == box_to_dict(ref) == box_to_dict(oracle_box(arr))

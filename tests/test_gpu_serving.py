@@ -118,3 +118,20 @@ def test_job_above_budget_runs_on_a_capped_plan():
     srv.close()
     assert r.info["prime_group"] < r.info["pn"]
     assert np.array_equal(r.limbs, alone(a))
+
+
+def test_config5_mix_with_a_large_job_equals_alone():
+    # jobs drawn like the serving workload's (n 4..32, 2-3 variables, degree 1-5, coefficients
+    # in [-2^16, 2^16]) plus one 32 x 32 trivariate degree-5 job, four at a time: every result
+    # in the mix is bit-identical to the same job solved alone
+    rng = W.rng_for(5, salt=7)
+    jobs = [W.config5_job(rng) for _ in range(10)]
+    jobs.insert(3, W.random_matrix(np.random.default_rng(5032), 32, (5, 5, 5), -65536, 65536))
+    srv = S.Server(memory_budget=120 << 30, slots=4)
+    futs = [srv.submit(a) for a in jobs]
+    results = [f.result(timeout=300) for f in futs]
+    srv.close()
+    assert srv.stats()["completed"] == len(jobs)
+    assert results[3].info["N"] == (256, 256, 256)
+    for a, r in zip(jobs, results):
+        assert np.array_equal(r.limbs, alone(a))

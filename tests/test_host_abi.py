@@ -352,3 +352,52 @@ def test_plan_with_coefficients_is_specialised_to_their_zero_pattern():
     other = arr * 3
     assert pdm.plan(5, (1, 1), host_coeffs=other, flags=pdm.HOST_ONLY).info["row_order"] == \
         spec["row_order"]
+
+
+def test_solve_stages_argument_errors():
+    lib = pdm.load_library()
+    arr = W.config1()
+    host = pdm.plan(4, (2, 2), host_coeffs=arr, flags=pdm.HOST_ONLY)
+    dummy = ctypes.c_void_p(256)
+    for b, e in ((0, 0), (3, 2), (-1, 2), (0, 7)):
+        assert lib.polydet_solve_stages(host.handle, b, e, dummy, dummy, dummy, 1 << 30,
+                                        None) == B.EINVAL
+    # a host-only plan cannot run even a valid range
+    assert lib.polydet_solve_stages(host.handle, 0, 6, dummy, dummy, dummy, 1 << 30,
+                                    None) == B.EINVAL
+    batch = pdm.plan_batch([arr], flags=pdm.HOST_ONLY)
+    assert lib.polydet_solve_stages(batch.handle, 0, 6, dummy, dummy, dummy, 1 << 30,
+                                    None) == B.EINVAL
+
+
+def _distinct_nonzero_entries(arr):
+    n = arr.shape[0]
+    boxes = {arr[i, j].tobytes() for i in range(n) for j in range(n) if np.any(arr[i, j])}
+    return len(boxes)
+
+
+@pytest.mark.parametrize("which", ["c2", "c3a", "c3b", "dup", "zero"])
+def test_plan_evaluates_each_distinct_entry_once(which):
+    # with the coefficients, entries with equal coefficient boxes are reduced and evaluated
+    # once (a Sylvester matrix repeats each coefficient of f and g along a diagonal)
+    if which == "c2":
+        arr = W.config2()
+    elif which == "c3a":
+        arr = W.config3a()
+    elif which == "c3b":
+        arr = W.config3b()[0]
+    elif which == "dup":
+        rng = np.random.default_rng(5)
+        base = W.random_matrix(rng, 3, (2, 1), -9, 9)
+        arr = np.tile(base, (3, 3, 1, 1))  # 9 x 9 with each entry repeated 9 times
+    else:
+        arr = np.zeros((4, 4, 2, 3), dtype=np.int64)
+    n, deg = B.shape_of(arr)
+    info = pdm.plan(n, deg, host_coeffs=arr, flags=pdm.HOST_ONLY).info
+    assert info["nslots"] == _distinct_nonzero_entries(arr)
+    if which == "c3a":
+        assert info["nslots"] == 24 and _distinct_nonzero_entries(arr) == 24
+    # without the coefficients, or with the full evaluation tensor, every entry is evaluated
+    assert pdm.plan(n, deg, coeff_bits=16, flags=pdm.HOST_ONLY).info["nslots"] == n * n
+    assert pdm.plan(n, deg, host_coeffs=arr,
+                    flags=pdm.HOST_ONLY | pdm.UNFUSED_EVAL).info["nslots"] == n * n
