@@ -1,19 +1,27 @@
-"""Throughput of the exact polynomial determinant on one MI355X.
+"""Throughput of exact polynomial determinants on one MI355X: batched against plain.
 
-Workload: a 12 x 12 matrix of trivariate polynomials of degree 3 per variable with
-coefficients uniform in [-1000, 1000] and 30% zero entries (seeded), determinant degree
-bound 36 per variable, 64^3 evaluation grid, 7 primes. One step = one full solve
-(reduce, evaluate, determinants, interpolate, reconstruct) with the coefficients already in
-HBM and a warm plan. The metric is modular determinants per second (prime x grid point),
-whole job; exact polynomial determinants per second are reported beside it.
+Default workload: 4096 matrices of uneven order (4..24), variable count (2..3) and degree
+(1..4 per variable), 10-40% zero entries, coefficients uniform in [-4096, 4096] (seeded). One
+step = one solve of the whole batch (reduce, evaluate, determinants, interpolate, reconstruct
+for every matrix) with the coefficients already in HBM and warm plans. The batched solve (the
+matrices' stages merged into a few launches per chunk) is captured once in a HIP graph and
+replayed; the plain path solves the same matrices one by one with the single-matrix launches.
+The metric is modular determinants per second (prime x grid point, summed over the batch),
+whole job; exact polynomial determinants per second and the batched/plain ratio are reported
+beside it. The line also carries the 12 x 12 trivariate single-matrix workload's kernel
+roofline (`roofline_config2`).
 
-Prints one JSON line (see the repository's benchmark contract).
+Prints one JSON line (the repository's benchmark contract). Other modes:
+  --workload config2   the single 12 x 12 trivariate matrix (64^3 grid, 7 primes)
+  --workload config5   the serving load (Poisson arrivals, p50/p99 latency)
+  --calibrate-alu      vector-ALU throughput probes (one JSON line)
 """
 import argparse
 import json
 import math
 import multiprocessing as mp
 import os
+import statistics
 import sys
 import time
 from concurrent.futures import TimeoutError as FutureTimeout
@@ -22,19 +30,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Peaks of MI355X used for the roofline (published figures; see the design notes).
+# Peaks of MI355X (published figures): 256 CUs at 2.4 GHz, HBM 8 TB/s. An elimination update
+# is issued as 4 multiply-class instructions (3 v_mad_u64_u32 + 1 v_mul_lo_u32), taken at the
+# fp64 vector rate (78.6 TFLOP/s = 64 lane-FMAs per clock per CU), and 1 plain 32-bit
+# instruction, taken at the fp32 vector rate (157.3 TFLOP/s = 128 lane-ops per clock per CU):
+# 1 / (4/64 + 1/128) = 14.2 updates per clock per CU.
 HBM_PEAK_GBS = 8000.0
 CU, CLOCK_HZ = 256, 2.4e9
-# one elimination update = 3 v_mad_u64_u32 + 1 v_mul_lo_u32 (fp64-FMA rate, 64 lanes/clk/CU)
-# + 2 plain 32-bit ops (128 lanes/clk/CU) -> 12.8 updates/clk/CU
-UPDATES_PER_CLK_CU = 1.0 / (4 / 64 + 2 / 128)
+UPDATES_PER_CLK_CU = 1.0 / (4 / 64 + 1 / 128)
 ALU_PEAK_UPDATES = CU * CLOCK_HZ * UPDATES_PER_CLK_CU
 
-
-# HBM bytes per launch of the fused elimination kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB copy (profiles/config2_hbm_traffic.md),
-# valid only for the kernel sources and tuning table they were taken with (their hash).
+# HBM bytes per launch of the 12 x 12 trivariate workload's elimination kernel, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB copy, valid only for the kernel sources
+# and tuning table they were taken with (their hash).
 DET_TRAFFIC = {"sources_sha256_16": "1809aef6fb7ee63f", "bytes": 186.2e6 + 14.7e6}
+
+STAGES = ("reduce", "evaluate", "determinants", "finalize", "interpolate", "reconstruct")
+
+
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_sources_hash() -> str:
@@ -66,16 +81,8 @@ def expand_bytes(pn: int, nnz: int, m, N) -> int:
     return 4 * pn * nnz * words
 
 
-def cpu_baseline(arr, D, pn, G):
-    """The oracle (pointwise integer Bareiss + exact interpolation) on the same matrix, all
-    host cores."""
-    from oracle import det as OD
+def host_cpu():
     cores = len(os.sched_getaffinity(0))
-    t0 = time.perf_counter()
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(cores) as pool:
-        OD.det_pointwise(arr, D, pool=pool)
-    t = time.perf_counter() - t0
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -85,19 +92,179 @@ def cpu_baseline(arr, D, pn, G):
                     break
     except OSError:
         pass
+    return cores, model
+
+
+def det_kernel_name(info, batched=False):
+    n, lanes = info["n"], info["det_lanes"]
+    m0 = info["deg"][0] + 1 if info["nvars"] else 1
+    paired = 2 <= m0 <= 4  # first-variable points j0, j0 + N0/2 built by two lanes
+    fused = ("det_fused_pair" if paired else "det_fused") + ("_batch" if batched else "") + \
+        f"_kernel<{n},{lanes}>"
+    if info["det_left_looking"]:
+        return f"det_ll_kernel<{n}> + repair {fused}"
+    return fused
+
+
+# ------------------------------------------------------------------------------- oracle legs
+def _oracle_one(args):
+    from oracle import det as OD
+    from oracle import plan as PL
+    i, a = args
+    n = a.shape[0]
+    deg = [a.shape[2 + v] - 1 for v in range(a.ndim - 2)]
+    OD.det_pointwise(a, PL.det_degree_bound_from_shape(n, deg))
+    return i
+
+
+def oracle_cost_s(n, deg):
+    """Rough single-core seconds of the pointwise oracle: node determinants plus the exact
+    inverse Vandermonde matrices (measured on this repository's oracle, within a factor 2)."""
+    nodes = math.prod(n * d + 1 for d in deg)
+    return nodes * n ** 3 * 0.4e-6 + sum(1.5 * ((n * d) / 64) ** 3 for d in deg)
+
+
+def cpu_baseline_batch(mats, infos, budget_s):
+    """The oracle on a bounded sample of the batch: matrices whose estimated oracle cost is
+    below one core-second, in seeded random order, solved by a pool over all host cores until
+    `budget_s` seconds have passed."""
+    import numpy as np
+    cores, model = host_cpu()
+    cheap = [i for i, a in enumerate(mats)
+             if oracle_cost_s(a.shape[0], [x - 1 for x in a.shape[2:]]) < 1.0]
+    order = list(np.random.default_rng(20).permutation(cheap))
+    ctx = mp.get_context("spawn")
+    done = []
+    t0 = time.perf_counter()
+    t_last = t0
+    with ctx.Pool(cores) as pool:
+        it = pool.imap_unordered(_oracle_one, ((int(i), mats[i]) for i in order), chunksize=1)
+        while True:
+            try:
+                i = it.next(timeout=max(0.01, budget_s - (time.perf_counter() - t0)))
+            except (StopIteration, mp.TimeoutError):
+                break
+            done.append(i)
+            t_last = time.perf_counter()
+            if t_last - t0 >= budget_s:
+                break
+        pool.terminate()
+    t = t_last - t0
+    moddets = sum(infos[i]["pn"] * infos[i]["G"] for i in done)
+    return {"value": moddets / t, "unit": "modular dets/s (equivalent)", "cores": cores,
+            "kind": "oracle",
+            "sample": (f"{len(done)} of the {len(mats)} matrices (seeded random order among the "
+                       f"{len(cheap)} whose pointwise oracle takes under about one core-second), "
+                       f"solved exactly in {t:.1f} s on {cores} processes ({model}); value = "
+                       "their pn*G summed / wall time, the same exact determinants expressed in "
+                       "the GPU metric's unit"),
+            "exact_dets_per_s": len(done) / t}
+
+
+def cpu_baseline_single(arr, D, pn, G):
+    """The oracle (pointwise integer Bareiss + exact interpolation) on the whole 12 x 12
+    trivariate matrix on all host cores, plus a single-core figure extrapolated from 2000 of
+    its node determinants."""
+    import numpy as np
+    from oracle import det as OD
+    cores, model = host_cpu()
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        OD.det_pointwise(arr, D, pool=pool)
+    t = time.perf_counter() - t0
+    nodes = OD.node_matrices(arr, D).reshape((-1,) + arr.shape[:2])
+    sample = [[[int(x) for x in r] for r in m] for m in nodes[:2000]]
+    t1 = time.perf_counter()
+    OD._det_rows(sample)
+    single = (time.perf_counter() - t1) * len(nodes) / len(sample)
     return {"value": pn * G / t, "unit": "modular dets/s (equivalent)", "cores": cores,
             "kind": "oracle",
-            "sample": (f"the whole 12x12 trivariate workload once: {int(__import__('numpy').prod([d + 1 for d in D]))} "
+            "sample": (f"the whole 12x12 trivariate matrix once: {int(np.prod([d + 1 for d in D]))} "
                        f"integer-node Bareiss determinants + exact interpolation in {t:.2f} s on "
-                       f"{cores} processes ({model}); value = pn*G / wall time, i.e. the same "
-                       f"exact polynomial determinant expressed in the GPU metric's unit"),
-            "exact_dets_per_s": 1.0 / t}
+                       f"{cores} processes ({model}); value = pn*G / wall time"),
+            "exact_dets_per_s": 1.0 / t,
+            "single_core_node_dets_s_extrapolated": single}
+
+
+# ----------------------------------------------------------------------- timing helpers
+def timed_each(fn, steps, stream):
+    """Run fn() `steps` times between events on `stream`; returns (total ms, per-step ms)."""
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return ev[0].elapsed_time(ev[steps]), per
+
+
+def stage_kernel_ms(pl, d_coeffs, out, ws, reps, stream):
+    """Mean device ms of each stage's kernels, each stage run `reps` times back to back on a
+    finished workspace (polydet_solve_stages) between two events: kernel durations without
+    any event between the kernels of a stage."""
+    import paper_2010_12117_amd as pdm
+    res = {}
+    for s, name in enumerate(STAGES):
+        total, _ = timed_each(lambda: pdm.solve_stages_device(pl, s, s + 1, d_coeffs, out, ws,
+                                                              stream=stream), reps, stream)
+        res[name] = total / reps
+    return res
+
+
+# ------------------------------------------------------------------------------ workloads
+def config2_roofline(reps=50):
+    """The 12 x 12 trivariate matrix: per-stage kernel durations and the elimination kernel's
+    ALU roofline."""
+    import numpy as np
+    import torch
+
+    import paper_2010_12117_amd as pdm
+    import workloads as W
+
+    arr = W.config2()
+    n, deg = 12, (3, 3, 3)
+    pl = pdm.plan(n, deg, host_coeffs=arr)
+    info = pl.info
+    pn, G = info["pn"], info["G"]
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
+    out = torch.empty((info["ncoeff"], info["limbs"]), dtype=torch.int32, device=dev)
+    ws = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(20):
+        pdm.solve_device(pl, d, out, ws)
+    total, per = timed_each(lambda: pdm.solve_device(pl, d, out, ws), reps, stream)
+    stage = stage_kernel_ms(pl, d, out, ws, reps, stream)
+    nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
+    work = pn * G * det_updates(n)
+    achieved = work / (stage["determinants"] / 1e3) / 1e12
+    traffic = (DET_TRAFFIC["bytes"]
+               if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
+    eval_bytes = expand_bytes(pn, nnz, [x + 1 for x in deg], list(info["N"]))
+    return {
+        "workload": "12x12 trivariate degree-3 matrix, coefficients U[-1000,1000], 30% zero "
+                    "entries, 64^3 grid, 7 primes",
+        "ms_per_solve": total / reps, "ms_per_solve_median": statistics.median(per),
+        "modular_dets_per_s": pn * G / (total / reps / 1e3),
+        "exact_dets_per_s": 1e3 / (total / reps),
+        "stage_kernel_ms": stage,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_UPDATES / 1e12,
+                     "unit": "T elimination-updates/s",
+                     "frac": achieved / (ALU_PEAK_UPDATES / 1e12), "traffic": traffic,
+                     "kernel": det_kernel_name(info), "work_per_launch": work,
+                     "avg_ms": stage["determinants"]},
+        "evaluate_roofline": {"bound": "hbm", "bytes_per_solve": eval_bytes,
+                              "achieved": eval_bytes / (stage["evaluate"] / 1e3) / 1e9,
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": eval_bytes / (stage["evaluate"] / 1e3) / 1e9 / HBM_PEAK_GBS},
+    }, (arr, info)
 
 
 def bench_batch(args):
-    """4096 matrices of uneven order (4..24), variable count (2..3) and degree (1..4) with
-    10-40% zero entries, coefficients in [-4096, 4096]: one batched solve (chunked persistent
-    launches) against the plain per-matrix path on the same GPU and inputs."""
     import numpy as np
     import torch
 
@@ -109,6 +276,8 @@ def bench_batch(args):
     pl = pdm.plan_batch(mats)
     plan_s = time.perf_counter() - t0
     plain = pdm.plan_batch(mats, flags=pdm.BATCH_PLAIN)
+    timing = pdm.plan_batch(mats, flags=pdm.STAGE_TIMING)
+    progress(f"plans built ({plan_s:.1f} s for the batched one)")
     infos = pl.infos
     co, oo = [], []
     c = o = 0
@@ -120,42 +289,152 @@ def bench_batch(args):
     dev = torch.device("cuda:0")
     d_coeffs = torch.from_numpy(np.concatenate([a.reshape(-1) for a in mats])).to(dev)
     d_out = torch.empty(o, dtype=torch.int32, device=dev)
-    ws = torch.empty(max(infos[0]["workspace_bytes"], plain.infos[0]["workspace_bytes"]),
-                     dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(infos[0]["workspace_bytes"], plain.infos[0]["workspace_bytes"],
+                         timing.infos[0]["workspace_bytes"]), dtype=torch.uint8, device=dev)
     moddets = sum(i["pn"] * i["G"] for i in infos)
     updates = sum(i["pn"] * i["G"] * det_updates(i["n"]) for i in infos)
+    stream = torch.cuda.Stream()
 
-    def timed(p, steps, warmup):
-        for _ in range(warmup):
-            pdm.solve_batch_device(p, d_coeffs, co, d_out, oo, workspace=ws)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            pdm.solve_batch_device(p, d_coeffs, co, d_out, oo, workspace=ws)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
+    def solve(p):
+        pdm.solve_batch_device(p, d_coeffs, co, d_out, oo, workspace=ws, stream=stream)
 
-    ms_batched = timed(pl, args.steps, args.warmup)
-    ms_plain = timed(plain, max(1, args.steps // 2), 1)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            solve(pl)
+        stream.synchronize()
+        ref = d_out.clone()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            solve(pl)
+        progress("warm-up and graph capture done")
+        total, per = timed_each(graph.replay, args.steps, stream)  # the timed region
+        ms_graph = total / args.steps
+        assert torch.equal(d_out, ref), "graph replay differs from the eager solve"
+        progress(f"batched (graph): {ms_graph:.1f} ms per solve")
+        _, per_eager = timed_each(lambda: solve(pl), args.eager_steps, stream)
+        progress(f"batched (eager): {statistics.median(per_eager):.1f} ms per solve")
+        for _ in range(args.warmup):
+            solve(plain)
+        _, per_plain = timed_each(lambda: solve(plain), args.plain_steps, stream)
+        assert torch.equal(d_out, ref), "plain path differs from the batched solve"
+        progress(f"plain: {statistics.median(per_plain):.1f} ms per solve")
+        solve(timing)
+        timing.stage_times()
+        solve(timing)
+        stage_ms, solves = timing.stage_times()
+        assert solves == 1
+    torch.cuda.synchronize()
+    det_ms = stage_ms["determinants"]
+    achieved = updates / (det_ms / 1e3) / 1e12
+    ms_plain = statistics.median(per_plain)
+    ms_med = statistics.median(per)
     line = {
-        "metric": "modular dets/sec (prime x point), exact poly dets/sec, batched vs plain, 1 GPU",
-        "value": moddets / (ms_batched / 1e3), "unit": "modular dets/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batched,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32 (mod p < 2^30)", "data": "synthetic (seeded)",
-        "config": {"workload": f"{len(mats)} matrices, n 4..24, 2-3 variables, degree 1-4, "
-                               "10-40% zero entries, coefficients U[-4096,4096]",
-                   "matrices": len(mats), "modular_dets": moddets, "updates": updates,
-                   "chunks_workspace_bytes": infos[0]["workspace_bytes"]},
-        "exact_dets_per_s": len(mats) / (ms_batched / 1e3),
+        "metric": "modular dets/sec (prime x point) and exact poly dets/sec, batched vs plain, "
+                  "1 GPU",
+        "value": moddets / (ms_graph / 1e3), "unit": "modular dets/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph,
+        "ms_per_step_median": ms_med, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 (mod p < 2^30)", "data": "synthetic (seeded)",
+        "config": {"workload": f"{len(mats)} matrices, n 4..24, 2-3 variables, degree 1-4 per "
+                               "variable, 10-40% zero entries, coefficients U[-4096,4096]",
+                   "matrices": len(mats), "modular_dets": moddets, "elimination_updates": updates,
+                   "workspace_bytes": infos[0]["workspace_bytes"]},
+        "exact_dets_per_s": len(mats) / (ms_graph / 1e3),
+        "batched": {"graph_ms_mean": ms_graph, "graph_ms_median": ms_med,
+                    "graph_ms_all": per, "eager_ms_median": statistics.median(per_eager),
+                    "eager_steps": args.eager_steps},
+        "plain": {"ms_median": ms_plain, "ms_mean": statistics.fmean(per_plain),
+                  "ms_all": per_plain, "steps": args.plain_steps},
         "plain_ms_per_step": ms_plain,
-        "batched_over_plain": ms_plain / ms_batched,
-        "elimination_updates_per_s": updates / (ms_batched / 1e3),
+        "batched_over_plain": ms_plain / ms_med,
+        "stage_ms_batched": stage_ms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_UPDATES / 1e12,
+                     "unit": "T elimination-updates/s",
+                     "frac": achieved / (ALU_PEAK_UPDATES / 1e12), "traffic": None,
+                     "kernel": "det_fused(_pair)_batch_kernel<n,lanes>: every elimination "
+                               "launch of one batched solve",
+                     "work_per_launch": updates, "avg_ms": det_ms,
+                     "avg_ms_source": "HIP events before and after each elimination launch of "
+                                      "one batched solve (sum)"},
         "plan_seconds": plan_s,
     }
+    progress("batch done; 12x12 trivariate roofline")
+    c2, (arr2, info2) = config2_roofline()
+    line["roofline_config2"] = c2
+    if not args.no_cpu_baseline:
+        progress("oracle on the host")
+        line["cpu_baseline"] = cpu_baseline_batch(mats, infos, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+def bench_single(args):
+    """The 12 x 12 trivariate matrix alone (64^3 grid, 7 primes)."""
+    import numpy as np
+    import torch
+
+    import paper_2010_12117_amd as pdm
+    import workloads as W
+    from oracle import plan as PL
+
+    arr = W.config2()
+    n, deg = 12, (3, 3, 3)
+    flags = 0
+    if args.det_lanes:
+        flags |= pdm.DET_LANES_LOG2(args.det_lanes.bit_length() - 1)
+    flags |= {"auto": 0, "left-looking": pdm.DET_LEFT_LOOKING,
+              "exchange": pdm.DET_EXCHANGE}[args.det_form]
+    pl = pdm.plan(n, deg, host_coeffs=arr, flags=flags)
+    info = pl.info
+    pn, G = info["pn"], info["G"]
+    dev = torch.device("cuda:0")
+    d = torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
+    out = torch.empty((info["ncoeff"], info["limbs"]), dtype=torch.int32, device=dev)
+    ws = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for _ in range(args.warmup):
+        pdm.solve_device(pl, d, out, ws)
+    total, per = timed_each(lambda: pdm.solve_device(pl, d, out, ws), args.steps, stream)
+    ms = total / args.steps
+    stage = stage_kernel_ms(pl, d, out, ws, args.steps, stream)
+    nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
+    work = pn * G * det_updates(n)
+    achieved = work / (stage["determinants"] / 1e3) / 1e12
+    traffic = (DET_TRAFFIC["bytes"]
+               if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
+    eval_bytes = expand_bytes(pn, nnz, [x + 1 for x in deg], list(info["N"]))
+    line = {
+        "metric": "modular dets/sec (prime x point), exact poly det end to end, 1 GPU",
+        "value": pn * G / (ms / 1e3), "unit": "modular dets/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "ms_per_step_median": statistics.median(per), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32 (mod p < 2^30)",
+        "data": "synthetic (seeded)",
+        "config": {"workload": "12x12 trivariate degree-3 matrix, coefficients U[-1000,1000], "
+                               "30% zero entries, 64^3 grid, 7 primes",
+                   "n": n, "nvars": 3, "deg": list(deg), "grid": list(info["N"]), "primes": pn,
+                   "nonzero_entries": nnz},
+        "exact_dets_per_s": 1e3 / ms,
+        "stage_kernel_ms": stage,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_UPDATES / 1e12,
+                     "unit": "T elimination-updates/s",
+                     "frac": achieved / (ALU_PEAK_UPDATES / 1e12), "traffic": traffic,
+                     "kernel": det_kernel_name(info), "work_per_launch": work,
+                     "avg_ms": stage["determinants"]},
+        "roofline_other": {"bound": "hbm", "achieved": eval_bytes / (stage["evaluate"] / 1e3) / 1e9,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": eval_bytes / (stage["evaluate"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+                           "traffic": None, "kernel": "expand_kernel (evaluation passes)",
+                           "bytes_per_solve": eval_bytes, "avg_ms": stage["evaluate"]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_single(arr, PL.det_degree_bound_from_shape(n, deg),
+                                                   pn, G)
     print(json.dumps(line), flush=True)
 
 
@@ -176,19 +455,18 @@ def bench_serving(args):
     budget = int(args.serve_budget_gb * (1 << 30))
 
     def run(rate, label):
-        srv = S.Server(memory_budget=budget, slots=args.slots)
+        srv = S.Server(memory_budget=budget, slots=args.slots, policy=args.policy)
         arr = S.poisson_arrivals(np.random.default_rng(77), len(jobs), rate) if rate else None
         t0 = time.perf_counter()
         last = t0
         futs = []
 
-        def progress():
+        def tick():
             nonlocal last
             now = time.perf_counter()
             if now - last > 15:
                 done = sum(f.done() for f in futs)
-                print(f"serving: {label}: {len(futs)} submitted, {done} done, "
-                      f"{now - t0:.0f} s", file=sys.stderr, flush=True)
+                progress(f"serving: {label}: {len(futs)} submitted, {done} done, {now - t0:.0f} s")
                 last = now
 
         for i, a in enumerate(jobs):
@@ -197,14 +475,14 @@ def bench_serving(args):
                 if wait > 0:
                     time.sleep(wait)
             futs.append(srv.submit(a))
-            progress()
+            tick()
         for f in futs:
             while True:
                 try:
                     f.result(timeout=5)
                     break
                 except FutureTimeout:
-                    progress()
+                    tick()
         makespan = time.perf_counter() - t0
         srv.close()
         st = srv.stats()
@@ -214,14 +492,14 @@ def bench_serving(args):
 
     run(0, "warm-up")  # plans, kernels, allocator
     torch.cuda.synchronize()
-    print("serving: warm-up done", file=sys.stderr, flush=True)
+    progress("serving: warm-up done")
     cap = run(0, "capacity")
     capacity = cap["jobs_per_s"]
-    print(f"serving: capacity {capacity:.1f} jobs/s", file=sys.stderr, flush=True)
+    progress(f"serving: capacity {capacity:.1f} jobs/s")
     out = {"capacity": cap}
     for rho in (0.5, 0.8):
         out[f"rho_{rho}"] = run(rho * capacity, f"rho {rho}")
-        print(f"serving: rho {rho} done", file=sys.stderr, flush=True)
+        progress(f"serving: rho {rho} done")
     line = {
         "metric": "serving: p50/p99 latency and throughput of exact determinant jobs, 1 GPU",
         "value": out["rho_0.8"]["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1,
@@ -229,166 +507,108 @@ def bench_serving(args):
         "config": {"workload": f"{len(jobs)} Poisson-arriving jobs, n 4..32, 2-3 variables, "
                                f"degree 1-5, coefficients U[-2^16,2^16], {large} of them "
                                "32x32 trivariate degree 5",
-                   "slots": args.slots, "memory_budget_gb": args.serve_budget_gb},
+                   "slots": args.slots, "memory_budget_gb": args.serve_budget_gb,
+                   "policy": args.policy},
         "results": out,
     }
     print(json.dumps(line), flush=True)
 
 
-def det_kernel_name(info):
-    n, lanes = info["n"], info["det_lanes"]
-    m0 = info["deg"][0] + 1 if info["nvars"] else 1
-    paired = 2 <= m0 <= 4  # first-variable points j0, j0 + N0/2 built by two lanes
-    fused = ("det_fused_pair_kernel" if paired else "det_fused_kernel") + f"<{n},{lanes}>"
-    if info["det_left_looking"]:
-        return f"det_ll_kernel<{n}> + repair {fused}"
-    return fused
+def calibrate_alu(args):
+    """Vector-ALU throughput probes (include/polydet_calibrate.h) and the elimination update's
+    peak derived from the published rates, beside the measured update rate."""
+    import ctypes
+
+    import torch
+
+    import paper_2010_12117_amd as pdm
+    lib = pdm.load_library()
+    lib.polydet_calibrate_alu.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    lib.polydet_calibrate_alu.restype = ctypes.c_int
+    names = ["mad_u64_u32", "mul_lo_u32", "add_u32", "elimination_update", "fma_f64", "fma_f32"]
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for probe, name in enumerate(names):
+        best = 0.0
+        for _ in range(3):
+            r = ctypes.c_double()
+            st = lib.polydet_calibrate_alu(probe, args.probe_blocks, args.probe_iters,
+                                           ctypes.byref(r), ctypes.c_void_p(stream.cuda_stream))
+            if st != 0:
+                raise RuntimeError(f"probe {name}: status {st}")
+            best = max(best, r.value)
+        out[name] = {"ops_per_s": best, "per_clk_per_cu": best / (CU * CLOCK_HZ)}
+        progress(f"{name}: {best / 1e12:.2f} T/s")
+    mad, mul = out["mad_u64_u32"]["per_clk_per_cu"], out["mul_lo_u32"]["per_clk_per_cu"]
+    add = out["add_u32"]["per_clk_per_cu"]
+    mix = 1.0 / (3 / mad + 1 / mul + 1 / add)  # updates per clock per CU from the measured rates
+    line = {"metric": "vector-ALU throughput probes", "unit": "ops/s", "probes": out,
+            "blocks": args.probe_blocks, "iters_per_thread": args.probe_iters,
+            "update_peak_derived": ALU_PEAK_UPDATES,
+            "update_peak_from_measured_instruction_rates": mix * CU * CLOCK_HZ,
+            "update_measured": out["elimination_update"]["ops_per_s"],
+            "clock_assumed_hz": CLOCK_HZ, "cus": CU}
+    print(json.dumps(line), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 200 solves at config 2, 2 batch solves at config 4)")
+                    help="timed steps (default: 5 batch solves; 200 single solves for config2)")
     ap.add_argument("--warmup", type=int, default=None,
-                    help="untimed steps first (default: 20 at config 2, 1 at config 4)")
+                    help="untimed steps first (default: 1 batch solve; 20 for config2)")
+    ap.add_argument("--plain-steps", type=int, default=None,
+                    help="timed solves of the plain per-matrix path (default: --steps)")
+    ap.add_argument("--eager-steps", type=int, default=2,
+                    help="timed eager (not graph-replayed) batched solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config4", "config5"],
-                    help="config2: the 12x12 trivariate matrix (default); config4: the batch "
-                         "of 4096 uneven matrices, batched against plain")
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of the oracle on the host (batch workload)")
+    ap.add_argument("--workload", default="config4", choices=["config4", "config2", "config5"],
+                    help="config4: the batch of 4096 uneven matrices, batched against plain "
+                         "(default); config2: the 12x12 trivariate matrix; config5: serving")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--jobs", type=int, default=2000, help="serving: number of jobs")
     ap.add_argument("--slots", type=int, default=4, help="serving: jobs in flight")
     ap.add_argument("--serve-budget-gb", type=float, default=96.0,
                     help="serving: device memory for jobs in flight")
+    ap.add_argument("--policy", default="sjf", choices=["sjf", "fifo"],
+                    help="serving: admission order")
     ap.add_argument("--det-lanes", type=int, default=0,
-                    help="lanes per determinant (1, 2, 4, 8, 16); 0 = the plan's choice")
+                    help="config2: lanes per determinant (1, 2, 4, 8, 16); 0 = the plan's choice")
     ap.add_argument("--det-form", default="auto", choices=["auto", "left-looking", "exchange"],
-                    help="elimination form of the determinant kernel (results are identical)")
+                    help="config2: elimination form of the determinant kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="before the timed loop, copy 1 GiB device to device once (a kernel of "
-                         "known traffic for scaling hardware byte counters)")
+                    help="config2: copy 1 GiB device to device once first (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
+    ap.add_argument("--calibrate-alu", action="store_true",
+                    help="run the vector-ALU throughput probes instead of a workload")
+    ap.add_argument("--probe-blocks", type=int, default=8192)
+    ap.add_argument("--probe-iters", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the determinant path is a single-GPU "
               "kernel pipeline, and no figure at several GPUs is measured", file=sys.stderr)
         sys.exit(2)
-
-    big = args.workload == "config4"
+    if args.calibrate_alu:
+        calibrate_alu(args)
+        return
+    single = args.workload == "config2"
     if args.steps is None:
-        args.steps = 2 if big else 200
+        args.steps = 200 if single else 5
     if args.warmup is None:
-        args.warmup = 1 if big else 20
+        args.warmup = 20 if single else 1
+    if args.plain_steps is None:
+        args.plain_steps = args.steps
     if args.workload == "config4":
         bench_batch(args)
-        return
-    if args.workload == "config5":
+    elif args.workload == "config5":
         bench_serving(args)
-        return
-
-    import numpy as np
-    import torch
-
-    import paper_2010_12117_amd as pdm
-    import workloads as W
-
-    arr = W.config2()
-    n, deg = 12, (3, 3, 3)
-    flags = 0
-    if args.det_lanes:
-        flags |= pdm.DET_LANES_LOG2(args.det_lanes.bit_length() - 1)
-    flags |= {"auto": 0, "left-looking": pdm.DET_LEFT_LOOKING,
-              "exchange": pdm.DET_EXCHANGE}[args.det_form]
-    # the timed plan records no stage events (each costs a few microseconds of device time
-    # between the kernels); a second plan with the library's stage events gives the kernels'
-    # own durations over a second pass of the same number of solves
-    pl = pdm.plan(n, deg, host_coeffs=arr, flags=flags)
-    pl_stages = pdm.plan(n, deg, host_coeffs=arr, flags=flags | pdm.STAGE_TIMING)
-    info = pl.info
-    pn, G = info["pn"], info["G"]
-    dev = torch.device("cuda:0")
-    d_coeffs = torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
-    out = torch.empty((info["ncoeff"], info["limbs"]), dtype=torch.int32, device=dev)
-    ws = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
-
-    if args.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    for _ in range(args.warmup):
-        pdm.solve_device(pl, d_coeffs, out, ws)
-    torch.cuda.synchronize()
-
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for i in range(args.steps):
-        pdm.solve_device(pl, d_coeffs, out, ws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    ms_per_step = total_ms / args.steps
-
-    # the same solves again with stage events: the duration of each stage's kernels
-    for _ in range(max(1, args.warmup // 4)):
-        pdm.solve_device(pl_stages, d_coeffs, out, ws)
-    torch.cuda.synchronize()
-    pl_stages.stage_times()  # discard the warm-up solves
-    s0 = torch.cuda.Event(enable_timing=True)
-    s1 = torch.cuda.Event(enable_timing=True)
-    s0.record(stream)
-    for i in range(args.steps):
-        pdm.solve_device(pl_stages, d_coeffs, out, ws)
-    s1.record(stream)
-    torch.cuda.synchronize()
-    staged_ms_per_step = s0.elapsed_time(s1) / args.steps
-    stage_ms, solves = pl_stages.stage_times()
-    assert solves == args.steps
-    value = pn * G / (ms_per_step / 1e3)
-
-    # roofline of each kernel class from its measured average duration
-    per = {k: v / args.steps for k, v in stage_ms.items()}
-    nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
-    det_work = pn * G * det_updates(n)
-    det_achieved = det_work / (per["determinants"] / 1e3) / 1e12
-    eval_bytes = expand_bytes(pn, nnz, [d + 1 for d in deg], list(info["N"]))
-    eval_gbs = eval_bytes / (per["evaluate"] / 1e3) / 1e9
-    traffic = (DET_TRAFFIC["bytes"]
-               if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
-    det_roof = {"bound": "alu", "achieved": det_achieved, "peak": ALU_PEAK_UPDATES / 1e12,
-                "unit": "T elimination-updates/s", "frac": det_achieved / (ALU_PEAK_UPDATES / 1e12),
-                "traffic": traffic, "kernel": det_kernel_name(info),
-                "work_per_launch": det_work, "avg_ms": per["determinants"]}
-    eval_roof = {"bound": "hbm", "achieved": eval_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": eval_gbs / HBM_PEAK_GBS, "traffic": None,
-                 "kernel": "expand_kernel<4> (2 launches)", "bytes_per_solve": eval_bytes,
-                 "avg_ms": per["evaluate"]}
-    dominant = det_roof if per["determinants"] >= per["evaluate"] else eval_roof
-
-    line = {
-        "metric": "modular dets/sec (prime x point), exact poly det end to end, 1 GPU",
-        "value": value, "unit": "modular dets/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32 (mod p < 2^30)",
-        "data": "synthetic (seeded)",
-        "config": {"workload": "12x12 trivariate degree-3 matrix, coefficients U[-1000,1000], "
-                               "30% zero entries, 64^3 grid, 7 primes",
-                   "n": n, "nvars": 3, "deg": list(deg), "grid": list(info["N"]), "primes": pn,
-                   "nonzero_entries": nnz},
-        "exact_dets_per_s": 1e3 / ms_per_step,
-        "ms_per_step_with_stage_events": staged_ms_per_step,
-        "stage_ms": per,
-        "roofline": dominant,
-        "roofline_other": eval_roof if dominant is det_roof else det_roof,
-    }
-    if not args.no_cpu_baseline:
-        from oracle import plan as PL
-        line["cpu_baseline"] = cpu_baseline(arr, PL.det_degree_bound_from_shape(n, deg), pn, G)
-    print(json.dumps(line), flush=True)
+    else:
+        bench_single(args)
 
 
 if __name__ == "__main__":
