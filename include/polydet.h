@@ -157,6 +157,8 @@ typedef struct polydet_plan_info {
   int64_t nslots;           /* entries that are reduced and evaluated: with host_coeffs, the
                              * distinct nonzero entries (entries with equal coefficient boxes,
                              * as in Sylvester matrices, are evaluated once); otherwise n*n */
+  double predicted_ms;      /* predicted device time of polydet_solve on this plan, from the
+                             * rates installed when the plan was built (polydet_set_rates) */
 } polydet_plan_info;
 
 typedef struct polydet_plan_s* polydet_plan_t;
@@ -297,6 +299,34 @@ typedef struct polydet_tuning {
 polydet_status polydet_set_tuning(const polydet_tuning* table);
 /* The table in use (all zeros when none is installed). EINVAL for NULL. */
 polydet_status polydet_get_tuning(polydet_tuning* out);
+
+/* Rates of the running-time prediction (Section 5, equation predictRunningTime, which
+ * predicts a solve from the prime count, the entries, the mean time to transform one entry
+ * and the replication factor of repeated entries; here every stage gets a term):
+ *   predicted = launches * launch_us
+ *             + (8 nslots T + 4 pn nslots T) / reduce_bytes_per_s
+ *             + sum over evaluation passes of 4 pn nslots (input + output box) / eval_bytes_per_s
+ *             + pn G (n-1) n (2n-1) / 6 / det_updates_per_s[class][n]
+ *             + sum over interpolation passes of 4 pn (input + output [+ denominators])
+ *               / intt_bytes_per_s
+ *             + ncoeff (pn (pn+1) / 2 + pn limbs) / garner_ops_per_s
+ * with T = prod (deg[v] + 1), class as in polydet_tuning. A value of 0 keeps the built-in rate.
+ * The table is process-wide and read when a plan is built; it is measured on the GPU by the
+ * package's calibration. It changes no result. */
+typedef struct polydet_rates {
+  double det_updates_per_s[2][POLYDET_TUNE_ORDERS];
+  double reduce_bytes_per_s;
+  double eval_bytes_per_s;
+  double intt_bytes_per_s;
+  double garner_ops_per_s;
+  double launch_us;
+} polydet_rates;
+
+/* Install a rate table (copied; NULL restores the built-in rates). EINVAL for a negative or
+ * non-finite entry. */
+polydet_status polydet_set_rates(const polydet_rates* rates);
+/* The table in use (built-in values where none was installed). EINVAL for NULL. */
+polydet_status polydet_get_rates(polydet_rates* out);
 
 void polydet_limits(int32_t* max_n, int32_t* max_vars, int32_t* max_grid_per_var,
                     int32_t* max_primes);

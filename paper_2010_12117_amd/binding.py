@@ -65,10 +65,23 @@ class PlanInfo(ctypes.Structure):
                 ("off_detv", ctypes.c_size_t), ("off_coef", ctypes.c_size_t),
                 ("row_order", ctypes.c_uint8 * 32), ("det_left_looking", ctypes.c_int32),
                 ("prime_group", ctypes.c_int32), ("coef_bytes", ctypes.c_size_t),
-                ("off_den", ctypes.c_size_t), ("nslots", ctypes.c_int64)]
+                ("off_den", ctypes.c_size_t), ("nslots", ctypes.c_int64),
+                ("predicted_ms", ctypes.c_double)]
 
 
 TUNE_ORDERS = 33
+
+
+class Rates(ctypes.Structure):
+    """polydet_rates: the running-time prediction's rates, 0 = built-in."""
+    _fields_ = [("det_updates_per_s", (ctypes.c_double * 33) * 2),
+                ("reduce_bytes_per_s", ctypes.c_double), ("eval_bytes_per_s", ctypes.c_double),
+                ("intt_bytes_per_s", ctypes.c_double), ("garner_ops_per_s", ctypes.c_double),
+                ("launch_us", ctypes.c_double)]
+
+
+RATE_SCALARS = ("reduce_bytes_per_s", "eval_bytes_per_s", "intt_bytes_per_s",
+                "garner_ops_per_s", "launch_us")
 
 
 class Tuning(ctypes.Structure):
@@ -83,7 +96,7 @@ EXPORTS = ["polydet_plan", "polydet_plan_batch", "polydet_plan_query", "polydet_
            "polydet_status_string", "polydet_last_error", "polydet_limits",
            "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning",
            "polydet_plan_capped", "polydet_solve_primes", "polydet_reconstruct",
-           "polydet_solve_stages"]
+           "polydet_solve_stages", "polydet_set_rates", "polydet_get_rates"]
 
 _lib = None
 
@@ -128,6 +141,8 @@ def load_library(path: str = LIB_PATH):
     lib.polydet_solve_primes.argtypes = [vp, vp, i32, i32, vp, sz, vp]
     lib.polydet_reconstruct.argtypes = [vp, vp, sz, vp, vp]
     lib.polydet_solve_stages.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
+    lib.polydet_set_rates.argtypes = [ctypes.POINTER(Rates)]
+    lib.polydet_get_rates.argtypes = [ctypes.POINTER(Rates)]
     for name in ["polydet_plan", "polydet_plan_batch", "polydet_plan_query",
                  "polydet_plan_primes", "polydet_solve", "polydet_solve_batch",
                  "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning",
@@ -136,6 +151,7 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     _install_default_tuning()
+    _install_default_rates()
     return lib
 
 
@@ -150,6 +166,46 @@ def _install_default_tuning():
         return
     with open(path) as f:
         set_tuning(json.load(f))
+
+
+# The prediction rates measured on the MI355X by calibrate.py, shipped with the package.
+# POLYDET_RATES names another file, or "builtin" for the library's own values.
+DEFAULT_RATES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "rates_gfx950.json")
+
+
+def _install_default_rates():
+    path = os.environ.get("POLYDET_RATES", DEFAULT_RATES)
+    if path == "builtin" or not os.path.exists(path):
+        return
+    with open(path) as f:
+        set_rates(json.load(f))
+
+
+def set_rates(table: Optional[dict]):
+    """Install the running-time prediction's rates: {"det_updates_per_s": {"paired"|"other":
+    {n: rate}}, "<scalar>": value, ...}; None restores the built-in rates."""
+    lib = load_library()
+    if table is None:
+        _check(lib.polydet_set_rates(None))
+        return
+    r = Rates()
+    for c, cls in enumerate(("paired", "other")):
+        for n, v in table.get("det_updates_per_s", {}).get(cls, {}).items():
+            r.det_updates_per_s[c][int(n)] = float(v)
+    for f in RATE_SCALARS:
+        setattr(r, f, float(table.get(f, 0.0)))
+    _check(lib.polydet_set_rates(ctypes.byref(r)))
+
+
+def get_rates() -> dict:
+    lib = load_library()
+    r = Rates()
+    _check(lib.polydet_get_rates(ctypes.byref(r)))
+    out = {"det_updates_per_s": {cls: {n: float(r.det_updates_per_s[c][n]) for n in range(1, 33)}
+                                 for c, cls in enumerate(("paired", "other"))}}
+    for f in RATE_SCALARS:
+        out[f] = float(getattr(r, f))
+    return out
 
 
 def set_tuning(table: Optional[dict]):

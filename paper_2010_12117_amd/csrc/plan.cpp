@@ -443,6 +443,7 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   }
   P.in_bytes = (size_t)P.nent * P.T * 8;
   P.out_bytes = (size_t)P.C * P.L * 4;
+  P.predicted_ms = predict_ms(P, get_rates());
   *out = std::move(P);
   return "";
 }

@@ -56,6 +56,23 @@ struct Tuning {
 void set_tuning(const Tuning& t);
 Tuning get_tuning();
 
+// Rates of the running-time prediction (polydet_rates); the defaults are rough MI355X values
+// used where no measured table is installed (0 entries of a table).
+struct Rates {
+  double det_updates_per_s[2][kMaxN + 1];
+  double reduce_bytes_per_s = 1.0e12;
+  double eval_bytes_per_s = 2.0e12;
+  double intt_bytes_per_s = 1.2e12;
+  double garner_ops_per_s = 2.0e12;
+  double launch_us = 4.0;
+  Rates() {
+    for (auto& c : det_updates_per_s)
+      for (auto& x : c) x = 3.5e12;
+  }
+};
+void set_rates(const Rates& r);
+Rates get_rates();
+
 // The descending table of primes p in (2^29, 2^30) with p = 1 mod 2^16 (784 of them).
 const std::vector<uint32_t>& prime_table();
 uint32_t primitive_root(uint32_t p);
@@ -111,7 +128,11 @@ struct MatPlan {
          off_coef = 0,
          off_iA = 0, off_iB = 0, ws_bytes = 0;
   size_t in_bytes = 0, out_bytes = 0;
+  double predicted_ms = 0;  // predict_ms with the rates installed when the plan was built
 };
+
+// Predicted device milliseconds of polydet_solve on plan P.
+double predict_ms(const MatPlan& P, const Rates& r);
 
 struct Plan {
   std::vector<MatPlan> mats;

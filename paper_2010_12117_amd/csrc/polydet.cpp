@@ -381,6 +381,7 @@ polydet_status polydet_plan_query(polydet_plan_t plan, int32_t index, polydet_pl
   out->off_coef = P.off_coef;
   out->off_den = P.off_den;
   out->nslots = P.nslot;
+  out->predicted_ms = P.predicted_ms;
   return POLYDET_OK;
 }
 
@@ -663,6 +664,46 @@ polydet_status polydet_get_tuning(polydet_tuning* out) {
       out->tile_points[c][n] = n <= pd::kMaxN ? t.tile_points[c][n] : 0;
     }
   }
+  return POLYDET_OK;
+}
+
+polydet_status polydet_set_rates(const polydet_rates* rates) {
+  pd::Rates r;
+  if (rates) {
+    auto ok = [](double v) { return v >= 0 && v < 1e300; };
+    for (int c = 0; c < 2; ++c) {
+      for (int n = 0; n <= pd::kMaxN; ++n) {
+        const double v = rates->det_updates_per_s[c][n];
+        if (!ok(v)) return fail(POLYDET_EINVAL, "rates: negative or non-finite entry");
+        if (v > 0) r.det_updates_per_s[c][n] = v;
+      }
+    }
+    const double* scal[5] = {&rates->reduce_bytes_per_s, &rates->eval_bytes_per_s,
+                             &rates->intt_bytes_per_s, &rates->garner_ops_per_s,
+                             &rates->launch_us};
+    double* dst[5] = {&r.reduce_bytes_per_s, &r.eval_bytes_per_s, &r.intt_bytes_per_s,
+                      &r.garner_ops_per_s, &r.launch_us};
+    for (int i = 0; i < 5; ++i) {
+      if (!ok(*scal[i])) return fail(POLYDET_EINVAL, "rates: negative or non-finite entry");
+      if (*scal[i] > 0) *dst[i] = *scal[i];
+    }
+  }
+  pd::set_rates(r);
+  return POLYDET_OK;
+}
+
+polydet_status polydet_get_rates(polydet_rates* out) {
+  if (!out) return fail(POLYDET_EINVAL, "rates: null output");
+  const pd::Rates r = pd::get_rates();
+  std::memset(out, 0, sizeof(*out));
+  for (int c = 0; c < 2; ++c) {
+    for (int n = 0; n < POLYDET_TUNE_ORDERS; ++n) out->det_updates_per_s[c][n] = r.det_updates_per_s[c][n];
+  }
+  out->reduce_bytes_per_s = r.reduce_bytes_per_s;
+  out->eval_bytes_per_s = r.eval_bytes_per_s;
+  out->intt_bytes_per_s = r.intt_bytes_per_s;
+  out->garner_ops_per_s = r.garner_ops_per_s;
+  out->launch_us = r.launch_us;
   return POLYDET_OK;
 }
 

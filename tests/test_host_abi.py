@@ -401,3 +401,29 @@ def test_plan_evaluates_each_distinct_entry_once(which):
     assert pdm.plan(n, deg, coeff_bits=16, flags=pdm.HOST_ONLY).info["nslots"] == n * n
     assert pdm.plan(n, deg, host_coeffs=arr,
                     flags=pdm.HOST_ONLY | pdm.UNFUSED_EVAL).info["nslots"] == n * n
+
+
+def test_running_time_prediction_follows_its_rates():
+    # the prediction is the sum of per-stage terms over the installed rates (polydet_rates):
+    # doubling the elimination rate halves the elimination term, a larger grid predicts more
+    saved = pdm.get_rates()
+    try:
+        pdm.set_rates(None)
+        base = pdm.get_rates()
+        arr = W.config2()
+        p0 = pdm.plan(12, (3, 3, 3), host_coeffs=arr, flags=pdm.HOST_ONLY).info
+        assert p0["predicted_ms"] > 0
+        det_term = p0["pn"] * p0["G"] * 506 / base["det_updates_per_s"]["paired"][12] * 1e3
+        doubled = {"det_updates_per_s": {"paired": {12: 2 * base["det_updates_per_s"]["paired"][12]}}}
+        pdm.set_rates(doubled)
+        p1 = pdm.plan(12, (3, 3, 3), host_coeffs=arr, flags=pdm.HOST_ONLY).info
+        assert abs((p0["predicted_ms"] - p1["predicted_ms"]) - det_term / 2) < 1e-9 * det_term
+        # built-in values stay where the table has zeros
+        assert pdm.get_rates()["launch_us"] == base["launch_us"]
+        small = pdm.plan(12, (1, 1, 1), host_coeffs=arr[..., :2, :2, :2], flags=pdm.HOST_ONLY).info
+        assert small["predicted_ms"] < p1["predicted_ms"]
+        with pytest.raises(pdm.PolydetError):
+            pdm.set_rates({"launch_us": -1.0})
+    finally:
+        pdm.set_rates(None)
+        pdm.set_rates({k: v for k, v in saved.items()})
