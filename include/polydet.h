@@ -213,6 +213,22 @@ polydet_status polydet_plan_primes(polydet_plan_t plan, int32_t index, uint32_t*
 polydet_status polydet_solve(polydet_plan_t plan, const int64_t* d_coeffs, uint32_t* d_out,
                              void* d_workspace, size_t workspace_bytes, void* stream);
 
+/* Size of the library's own workspace for polydet_solve_noalloc (128 MiB per device). */
+#define POLYDET_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* polydet_solve without a caller's workspace and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The workspace is a device array of the library,
+ * POLYDET_NOALLOC_SCRATCH_BYTES on every device it runs on, held until the process ends;
+ * its address is looked up on the first call on each device. The caller still passes the
+ * coefficients and the output (as for polydet_solve). Every call on one device shares that
+ * array and leaves its contents behind: calls that overlap on one device (several streams or
+ * threads) race on it and must be ordered by the caller. EINVAL when the plan's
+ * workspace_bytes exceeds POLYDET_NOALLOC_SCRATCH_BYTES (nothing is enqueued); otherwise as
+ * polydet_solve. */
+polydet_status polydet_solve_noalloc(polydet_plan_t plan, const int64_t* d_coeffs,
+                                     uint32_t* d_out, void* stream);
+
 /* Solve every matrix of a batch plan.
  * d_coeffs: device int64 buffer holding every matrix's coefficients; coeff_offsets[i]
  * (host, in int64 elements) is where matrix i starts. d_out: device uint32 buffer;

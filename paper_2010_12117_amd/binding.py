@@ -96,7 +96,11 @@ EXPORTS = ["polydet_plan", "polydet_plan_batch", "polydet_plan_query", "polydet_
            "polydet_status_string", "polydet_last_error", "polydet_limits",
            "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning",
            "polydet_plan_capped", "polydet_solve_primes", "polydet_reconstruct",
-           "polydet_solve_stages", "polydet_set_rates", "polydet_get_rates"]
+           "polydet_solve_stages", "polydet_set_rates", "polydet_get_rates",
+           "polydet_solve_noalloc"]
+
+# polydet_solve_noalloc's own workspace per device (POLYDET_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 _lib = None
 
@@ -143,11 +147,13 @@ def load_library(path: str = LIB_PATH):
     lib.polydet_solve_stages.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
     lib.polydet_set_rates.argtypes = [ctypes.POINTER(Rates)]
     lib.polydet_get_rates.argtypes = [ctypes.POINTER(Rates)]
+    lib.polydet_solve_noalloc.argtypes = [vp, vp, vp, vp]
     for name in ["polydet_plan", "polydet_plan_batch", "polydet_plan_query",
                  "polydet_plan_primes", "polydet_solve", "polydet_solve_batch",
                  "polydet_stage_times", "polydet_set_tuning", "polydet_get_tuning",
                  "polydet_plan_capped", "polydet_solve_primes", "polydet_reconstruct",
-           "polydet_solve_stages"]:
+                 "polydet_solve_stages", "polydet_set_rates", "polydet_get_rates",
+                 "polydet_solve_noalloc"]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     _install_default_tuning()
@@ -396,6 +402,24 @@ def solve_device(pl: Plan, d_coeffs, d_out=None, workspace=None, stream=None):
                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                              _stream_ptr(torch, stream)))
     return d_out, workspace
+
+
+def solve_noalloc_device(pl: Plan, d_coeffs, d_out, stream=None):
+    """Enqueue polydet_solve_noalloc: a solve whose workspace is the library's own device array
+    (no allocation by the library; the caller passes the coefficients and the output)."""
+    torch = _torch()
+    info = pl.info
+    if d_coeffs.dtype != torch.int64 or not d_coeffs.is_cuda or not d_coeffs.is_contiguous():
+        raise ValueError("coefficients must be a contiguous int64 device tensor")
+    if d_coeffs.numel() * 8 != info["in_bytes"]:
+        raise ValueError("coefficient tensor size does not match the plan")
+    if d_out.numel() * 4 < info["out_bytes"]:
+        raise ValueError("output tensor smaller than the plan's output")
+    lib = load_library()
+    _check(lib.polydet_solve_noalloc(pl.handle, ctypes.c_void_p(d_coeffs.data_ptr()),
+                                     ctypes.c_void_p(d_out.data_ptr()),
+                                     _stream_ptr(torch, stream)))
+    return d_out
 
 
 def solve_stages_device(pl: Plan, stage_begin: int, stage_end: int, d_coeffs, d_out, workspace,
