@@ -17,22 +17,29 @@ constexpr int kEvalChunk = 8;  // entries per scheduling window of the fused eva
 // ------------------------------------------------------------------------------------
 // S3: determinant of the n x n matrix at every (prime, grid point).
 //
-// Division-free condensation (Chio's rule, the condensation the paper adopts in its
-// DET step, Section 3.2): with pivot pi = A[k][k], every later row becomes
-//   A[i][j] <- pi A[i][j] - A[i][k] A[k][j]   (j > k),
-// which multiplies the determinant by pi once per updated row. After n - 1 steps the
-// pivots pi_0..pi_{n-1} are the diagonal of a triangular matrix, so
-//   det = sign * pi_{n-1} / prod_{k <= n-3} pi_k^{n-k-2},
-// and the denominator is the product of the prefix products e_j = pi_0 .. pi_j for
-// j <= n-3. One inverse (Fermat) per determinant replaces one per step. The pivot is the
-// first nonzero entry scanning down column k; each exchange flips the sign; a column with
-// no pivot gives determinant 0. Each update is one reduction of two products (mm2).
+// Division-free condensation, two columns per step. The paper's DET step (Section 3.2)
+// condenses one column at a time (Chio's rule: with pivot pi = A[k][k], every later entry
+// becomes pi A[i][j] - A[i][k] A[k][j]). Here two columns go at once, by Sylvester's
+// determinant identity as used in Bareiss's two-step fraction-free elimination (Bareiss 1968):
+// with the 2 x 2 leading minor D = A[k][k] A[k+1][k+1] - A[k][k+1] A[k+1][k], every entry
+// i, j >= k + 2 becomes the 3 x 3 minor bordered by row i and column j,
+//   A[i][j] <- D A[i][j] - A[i][k+1] u_j + A[i][k] v_j,
+//   u_j = A[k][k] A[k+1][j] - A[k+1][k] A[k][j],   v_j = A[k][k+1] A[k+1][j] - A[k+1][k+1] A[k][j],
+// and the condensed matrix of order m - 2 has determinant det(A) D^(m-3) (m = n - k, the
+// order before the step). Three products under one Montgomery reduction replace the two
+// reductions of two single steps. The last one or two rows finish directly (an entry, or a
+// 2 x 2 determinant), so det = sign * last / prod_s D_s^(m_s - 3), and the denominator is
+// accumulated with prefix products of the D_s. One inverse (Fermat) per determinant remains.
+// Pivoting: the first nonzero entry scanning down column k becomes A[k][k]; if then D = 0,
+// the first later row i whose single-step value A[k][k] A[i][k+1] - A[i][k] A[k][k+1] is
+// nonzero takes the place of row k + 1 (D becomes that value). Each exchange flips the sign;
+// no such row (or no pivot in column k) gives determinant 0.
 //
 // Mapping: GL lanes cooperate on one matrix (GL = 1: one matrix per lane). Lane t of a
 // group holds columns t, t + GL, t + 2 GL, ... of all n rows in registers (a[c][i] is
-// A[i][c GL + t]), so every index below is static after unrolling. The owner of column k
-// (lane k mod GL) finds the pivot row and broadcasts the row index, the pivot and the
-// multipliers to its group with DPP moves; row exchanges are register selects.
+// A[i][c GL + t]), so every index below is static after unrolling. The owners of columns k
+// and k + 1 broadcast the pivot rows' and each row's two factors to their group with DPP
+// moves; row exchanges are register selects.
 // ------------------------------------------------------------------------------------
 
 // Lane `src` of each aligned group of GL lanes to the whole group, as DPP moves (VALU, no
@@ -98,18 +105,48 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
 }
 
 // The determinant of the matrix held by the lane group as a quotient num / den (Montgomery
-// form): num = sign * pi_{n-1} (0 when some column has no pivot) and den = prod_{k<=n-3}
-// pi_k^{n-k-2} (the representative of 1 for a singular matrix, so that den is never 0).
-// The division is left to a later pass (the first interpolation pass, or finalize_kernel for
-// integer matrices and batches), which inverts the denominators of several points with one
-// exponentiation. Every lane of the group returns the pair; all lanes of the wave
-// must call this together (lane broadcasts).
-// Entries may come in unreduced, in [0, 2p), and stay so: each step reduces only its pivot
-// column (for the zero test, the exchange and the multipliers), and the updates use
-// mm2_lazy, whose sum of products stays below 4 p^2 < p R with p < 2^30.
+// form): num = sign * (the last entry, or the last 2 x 2 determinant), 0 when the matrix is
+// singular; den = prod_s D_s^(m_s - 3) (the representative of 1 for a singular matrix, so
+// that den is never 0). The division is left to a later pass (the first interpolation pass,
+// or finalize_kernel for integer matrices and batches), which inverts the denominators of
+// several points with one exponentiation. Every lane of the group returns the pair; all lanes
+// of the wave must call this together (lane broadcasts).
+// Entries may come in unreduced, in [0, 2p), and stay so: each step reduces only its two
+// pivot columns (for the zero tests, the exchanges and the row factors), the column factors
+// u_j, v_j are reduced, and the update sums three products with one unreduced factor
+// (mm3_lazy: below 4 p^2 < p R for p < 2^30).
 struct DetFrac {
   uint32_t num, den;
 };
+
+// Makes A[k][k] nonzero by exchanging row k with the first later row whose column-k entry is
+// nonzero (column k reduced); no such row marks the matrix dead.
+template <int N, int GL>
+__device__ __forceinline__ void pivot_column(uint32_t (&a)[(N + GL - 1) / GL][N], int k,
+                                             uint32_t& flip, bool& dead) {
+  constexpr int C = (N + GL - 1) / GL;
+  const int s = k / GL, o = k % GL;
+  const uint32_t zero_piv = bcast<GL>(a[s][k] == 0u ? 1u : 0u, o);
+  if (__any(zero_piv != 0u)) {
+    int r = N;
+#pragma unroll
+    for (int i = N - 1; i > k; --i) r = (a[s][i] != 0u) ? i : r;
+    r = (int)bcast<GL>((uint32_t)r, o);
+    if (!zero_piv) r = k;
+    dead = dead || (r == N);
+    flip ^= (r != k && r != N) ? 1u : 0u;
+#pragma unroll
+    for (int i = k + 1; i < N; ++i) {
+      const bool sw = (r == i);
+#pragma unroll
+      for (int c = s; c < C; ++c) {
+        const uint32_t x = a[c][k], y = a[c][i];
+        a[c][k] = sw ? y : x;
+        a[c][i] = sw ? x : y;
+      }
+    }
+  }
+}
 
 template <int N, int GL>
 __device__ __forceinline__ DetFrac eliminate(uint32_t (&a)[(N + GL - 1) / GL][N], uint32_t p,
@@ -117,48 +154,98 @@ __device__ __forceinline__ DetFrac eliminate(uint32_t (&a)[(N + GL - 1) / GL][N]
   constexpr int C = (N + GL - 1) / GL;
   uint32_t flip = 0;
   bool dead = false;
-  uint32_t e = one, Q = one;
+  uint32_t e = one, Q = one;  // e = D_0 .. D_s; Q accumulates the denominator
 #pragma unroll
-  for (int k = 0; k < N - 1; ++k) {
-    const int s = k / GL, o = k % GL;
-    // slot s holds column k in lane o of the group: reduce it (the other lanes' columns in
-    // the slot come along; a reduced value is a valid unreduced one)
+  for (int k = 0; k + 2 < N; k += 2) {
+    const int s0 = k / GL, o0 = k % GL;
+    const int s1 = (k + 1) / GL, o1 = (k + 1) % GL;
+    // reduce the two pivot columns (with them the other columns of their slots, harmlessly)
 #pragma unroll
-    for (int i = k; i < N; ++i) a[s][i] = fold(a[s][i], p);
-    const uint32_t zero_piv = bcast<GL>(a[s][k] == 0u ? 1u : 0u, o);
-    if (__any(zero_piv != 0u)) {
+    for (int i = k; i < N; ++i) {
+      a[s0][i] = fold(a[s0][i], p);
+      if (s1 != s0) a[s1][i] = fold(a[s1][i], p);
+    }
+    pivot_column<N, GL>(a, k, flip, dead);
+    const uint32_t a00 = bcast<GL>(a[s0][k], o0), a01 = bcast<GL>(a[s1][k], o1);
+    uint32_t a10 = bcast<GL>(a[s0][k + 1], o0), a11 = bcast<GL>(a[s1][k + 1], o1);
+    uint32_t D = mm2(a00, a11, p - a10, a01, p, pinv);
+    if (__any(D == 0u && !dead)) {
+      // a vanishing 2 x 2 minor: bring up the first row whose single-step value is nonzero
       int r = N;
 #pragma unroll
-      for (int i = N - 1; i > k; --i) r = (a[s][i] != 0u) ? i : r;
-      r = (int)bcast<GL>((uint32_t)r, o);
-      if (!zero_piv) r = k;
+      for (int i = N - 1; i > k + 1; --i) {
+        const uint32_t b = mm2(a00, bcast<GL>(a[s1][i], o1), p - bcast<GL>(a[s0][i], o0), a01,
+                               p, pinv);
+        r = (b != 0u) ? i : r;
+      }
+      if (D != 0u) r = k + 1;
       dead = dead || (r == N);
-      flip ^= (r != k && r != N) ? 1u : 0u;
+      flip ^= (r != k + 1 && r != N) ? 1u : 0u;
 #pragma unroll
-      for (int i = k + 1; i < N; ++i) {
+      for (int i = k + 2; i < N; ++i) {
         const bool sw = (r == i);
 #pragma unroll
-        for (int c = s; c < C; ++c) {
-          const uint32_t x = a[c][k], y = a[c][i];
-          a[c][k] = sw ? y : x;
+        for (int c = s0; c < C; ++c) {
+          const uint32_t x = a[c][k + 1], y = a[c][i];
+          a[c][k + 1] = sw ? y : x;
           a[c][i] = sw ? x : y;
         }
       }
+      a10 = bcast<GL>(a[s0][k + 1], o0);
+      a11 = bcast<GL>(a[s1][k + 1], o1);
+      D = mm2(a00, a11, p - a10, a01, p, pinv);
     }
-    const uint32_t piv = bcast<GL>(a[s][k], o);
+    // the slots that hold columns >= k + 2 (a slot's lanes below that column compute values
+    // nobody reads)
+    const int sf = (k + 2) / GL;
+    if constexpr (GL == 1) {
+      // one lane per matrix: column by column, so that only one column's factors are live
 #pragma unroll
-    for (int i = k + 1; i < N; ++i) {
-      const uint32_t mi = p - bcast<GL>(a[s][i], o);  // -A[i][k]; p stands for 0
+      for (int c = k + 2; c < N; ++c) {
+        const uint32_t nu = p - fold(mm2_lazy(a00, a[c][k + 1], p - a10, a[c][k], p, pinv), p);
+        const uint32_t v = fold(mm2_lazy(a01, a[c][k + 1], p - a11, a[c][k], p, pinv), p);
 #pragma unroll
-      for (int c = s; c < C; ++c) a[c][i] = mm2_lazy(piv, a[c][i], mi, a[c][k], p, pinv);
+        for (int i = k + 2; i < N; ++i)
+          a[c][i] = mm3_lazy(D, a[c][i], a[k + 1][i], nu, a[k][i], v, p, pinv);
+      }
+    } else {
+      uint32_t nu[C], v[C];
+#pragma unroll
+      for (int c = sf; c < C; ++c) {
+        nu[c] = p - fold(mm2_lazy(a00, a[c][k + 1], p - a10, a[c][k], p, pinv), p);
+        v[c] = fold(mm2_lazy(a01, a[c][k + 1], p - a11, a[c][k], p, pinv), p);
+      }
+#pragma unroll
+      for (int i = k + 2; i < N; ++i) {
+        const uint32_t f0 = bcast<GL>(a[s0][i], o0), f1 = bcast<GL>(a[s1][i], o1);
+#pragma unroll
+        for (int c = sf; c < C; ++c) a[c][i] = mm3_lazy(D, a[c][i], f1, nu[c], f0, v[c], p, pinv);
+      }
     }
-    if (k <= N - 3) {
-      e = mm(e, piv, p, pinv);
+    // den = prod_s D_s^(m_s - 3) as prod_s e_s^(w_s), e_s = D_0 .. D_s: w_s = 2 while another
+    // two-column step follows, and m_s - 3 (0 or 1) for the last one
+    e = mm(e, D, p, pinv);
+    if (k + 4 < N) {
+      Q = mm(Q, e, p, pinv);
+      Q = mm(Q, e, p, pinv);
+    } else if (N - k == 4) {
       Q = mm(Q, e, p, pinv);
     }
   }
-  constexpr int sl = (N - 1) / GL, ol = (N - 1) % GL;
-  const uint32_t last = fold(bcast<GL>(a[sl][N - 1], ol), p);
+  constexpr int kl = (N - 1) & ~1;  // first row of the last block: N - 1 (odd N) or N - 2
+  uint32_t last;
+  if constexpr (N - kl == 2) {
+    // the remaining 2 x 2 block: its determinant directly
+    constexpr int s0 = kl / GL, o0 = kl % GL, s1 = (kl + 1) / GL, o1 = (kl + 1) % GL;
+    const uint32_t a00 = fold(bcast<GL>(a[s0][kl], o0), p);
+    const uint32_t a10 = fold(bcast<GL>(a[s0][kl + 1], o0), p);
+    const uint32_t a01 = fold(bcast<GL>(a[s1][kl], o1), p);
+    const uint32_t a11 = fold(bcast<GL>(a[s1][kl + 1], o1), p);
+    last = mm2(a00, a11, p - a10, a01, p, pinv);
+  } else {
+    constexpr int sl = kl / GL, ol = kl % GL;
+    last = fold(bcast<GL>(a[sl][kl], ol), p);
+  }
   dead = dead || (last == 0u);
   DetFrac f;
   f.num = dead ? 0u : (flip ? negm(last, p) : last);

@@ -9,7 +9,8 @@
 // elimination update fold two products into one reduction. Since p < 2^30, the sum may even
 // have one factor of each product below 2p (then t < 4 p^2 < p R): the elimination keeps its
 // entries unreduced in [0, 2p) and skips the conditional subtraction of most updates
-// (mm2_lazy).
+// (mm2_lazy). Its two-step update sums three products, one of them with an unreduced factor,
+// under one reduction: 2 p^2 + p^2 + p^2 = 4 p^2 < p R again (mm3_lazy).
 //
 // On gfx950 v_mad_u64_u32 and v_mul_lo_u32 issue at the fp64-FMA rate and plain 32-bit
 // ALU ops at twice that, so one REDC costs one mul_lo, one mad_u64 and two plain ops.
@@ -56,6 +57,15 @@ PD_HD uint32_t mm2_lazy(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t
   // The mask changes nothing (the value is below 2p < 2^31) but keeps it a 32-bit value:
   // without it the compiler widens the next product's operand to the 64-bit shifted sum
   // (its high half known zero) and holds two registers per entry.
+  return (uint32_t)((t + (uint64_t)m * p) >> 32) & 0x7FFFFFFFu;
+}
+
+// (a b + c d + e f) / R in [0, 2p) with b < 2p and every other operand <= p:
+// t < 2 p^2 + 2 p^2 = 4 p^2 < p R, three products for one reduction.
+PD_HD uint32_t mm3_lazy(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e, uint32_t f,
+                        uint32_t p, uint32_t pinv) {
+  const uint64_t t = (uint64_t)a * b + (uint64_t)c * d + (uint64_t)e * f;
+  const uint32_t m = (uint32_t)t * pinv;
   return (uint32_t)((t + (uint64_t)m * p) >> 32) & 0x7FFFFFFFu;
 }
 

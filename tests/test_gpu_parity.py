@@ -52,10 +52,18 @@ def det_regions(pl, ws):
 
 
 def assert_same_fractions(pla, wsa, plb, wsb):
-    """Both solves left the same numerator and denominator at every (prime, point)."""
+    """Both solves left the same determinant num / den mod p at every (prime, point), and no
+    zero denominator. (The two-column condensation and the left-looking pass reach the same
+    quotient through different numerators and denominators, so the pairs are compared by
+    cross-multiplication: num_a den_b = num_b den_a mod p; the Montgomery factors cancel.)"""
     na, da = det_regions(pla, wsa)
     nb, db = det_regions(plb, wsb)
-    assert np.array_equal(na, nb) and np.array_equal(da, db)
+    assert pla.info["primes"] == plb.info["primes"]
+    assert da.all() and db.all()
+    for q, p in enumerate(pla.info["primes"]):
+        lhs = na[q].astype(np.uint64) * db[q].astype(np.uint64) % np.uint64(p)
+        rhs = nb[q].astype(np.uint64) * da[q].astype(np.uint64) % np.uint64(p)
+        assert np.array_equal(lhs, rhs)
 
 
 def oracle_box(arr):
