@@ -30,15 +30,46 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Peaks of MI355X (published figures): 256 CUs at 2.4 GHz, HBM 8 TB/s. An elimination update
-# is issued as 4 multiply-class instructions (3 v_mad_u64_u32 + 1 v_mul_lo_u32), taken at the
-# fp64 vector rate (78.6 TFLOP/s = 64 lane-FMAs per clock per CU), and 1 plain 32-bit
-# instruction, taken at the fp32 vector rate (157.3 TFLOP/s = 128 lane-ops per clock per CU):
-# 1 / (4/64 + 1/128) = 14.2 updates per clock per CU.
+# Peaks of MI355X (published figures): 256 CUs at 2.4 GHz, HBM 8 TB/s. The elimination is
+# bound by integer vector arithmetic. 64-bit integer multiply-adds (v_mad_u64_u32) and 32-bit
+# multiplies (v_mul_lo_u32) issue at the fp64 vector rate (78.6 TFLOP/s = 64 lane-FMAs per
+# clock per CU); plain 32-bit operations at the fp32 vector rate (157.3 TFLOP/s = 128 lane-ops
+# per clock per CU). So one lane-op costs 1/64 or 1/128 of a CU-clock.
 HBM_PEAK_GBS = 8000.0
 CU, CLOCK_HZ = 256, 2.4e9
-UPDATES_PER_CLK_CU = 1.0 / (4 / 64 + 1 / 128)
-ALU_PEAK_UPDATES = CU * CLOCK_HZ * UPDATES_PER_CLK_CU
+MULT_CLK, PLAIN_CLK = 1 / 64, 1 / 128
+# A single-step (Chio) update, 4 multiply-class + 1 plain op, would peak at 14.2 per
+# CU-clock, 8.74e12/s: the ceiling of a one-column-per-step elimination, kept for comparison.
+SINGLE_STEP_PEAK_UPDATES = CU * CLOCK_HZ / (4 * MULT_CLK + 1 * PLAIN_CLK)
+
+
+def det_issue_clk(n: int) -> float:
+    """Minimal issue cost in CU-clocks per lane of one determinant of order n by two-column
+    condensation, the kernels' algorithm: at each order m = n, n - 2, ... >= 3, the (m-2)^2
+    three-product updates (4 v_mad_u64_u32 + 1 v_mul_lo_u32 + 1 mask each) and, for each of
+    the m - 2 columns, its two factors (two reductions of two products, 3 mad + 1 mul_lo + 1
+    mask each, two conditional subtractions of 2 ops and one negation); an even order ends with
+    a 2 x 2 determinant (3 mad + 1 mul_lo, a conditional subtraction). Pivot search, the
+    denominators and the evaluation fused into the same kernel are not counted."""
+    clk = 0.0
+    m = n
+    while m >= 3:
+        clk += (m - 2) ** 2 * (5 * MULT_CLK + 1 * PLAIN_CLK)
+        clk += (m - 2) * (8 * MULT_CLK + 7 * PLAIN_CLK)
+        m -= 2
+    if m == 2:
+        clk += 4 * MULT_CLK + 2 * PLAIN_CLK
+    return clk
+
+
+def alu_peak_updates(work):
+    """Peak elimination-updates per second (the determinant's sum_{m<n} m^2 modular
+    multiply-subtracts, the algorithmic unit) of a mix of determinants, `work` = [(n, dets)]:
+    the chip issuing the kernels' minimal instruction mix on every CU every clock."""
+    upd = sum(d * det_updates(n) for n, d in work)
+    clk = sum(d * det_issue_clk(n) for n, d in work)
+    return upd / clk * CU * CLOCK_HZ if clk else 0.0
+
 
 # HBM bytes per launch of the 12 x 12 trivariate workload's elimination kernel, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB copy, valid only for the kernel sources
@@ -242,6 +273,7 @@ def config2_roofline(reps=50):
     nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
     work = pn * G * det_updates(n)
     achieved = work / (stage["determinants"] / 1e3) / 1e12
+    peak = alu_peak_updates([(n, pn * G)]) / 1e12
     traffic = (DET_TRAFFIC["bytes"]
                if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
     eval_bytes = expand_bytes(pn, nnz, [x + 1 for x in deg], list(info["N"]))
@@ -252,11 +284,11 @@ def config2_roofline(reps=50):
         "modular_dets_per_s": pn * G / (total / reps / 1e3),
         "exact_dets_per_s": 1e3 / (total / reps),
         "stage_kernel_ms": stage,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_UPDATES / 1e12,
-                     "unit": "T elimination-updates/s",
-                     "frac": achieved / (ALU_PEAK_UPDATES / 1e12), "traffic": traffic,
-                     "kernel": det_kernel_name(info), "work_per_launch": work,
-                     "avg_ms": stage["determinants"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "T elimination-updates/s", "frac": achieved / peak,
+                     "traffic": traffic, "kernel": det_kernel_name(info),
+                     "work_per_launch": work, "avg_ms": stage["determinants"],
+                     "frac_of_single_step_peak": achieved / (SINGLE_STEP_PEAK_UPDATES / 1e12)},
         "evaluate_roofline": {"bound": "hbm", "bytes_per_solve": eval_bytes,
                               "achieved": eval_bytes / (stage["evaluate"] / 1e3) / 1e9,
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -276,6 +308,7 @@ def bench_batch(args):
     pl = pdm.plan_batch(mats)
     plan_s = time.perf_counter() - t0
     plain = pdm.plan_batch(mats, flags=pdm.BATCH_PLAIN)
+    side = plan_batch_streams(pdm, mats, 4)  # elimination launches side by side, 4 streams
     timing = pdm.plan_batch(mats, flags=pdm.STAGE_TIMING)
     progress(f"plans built ({plan_s:.1f} s for the batched one)")
     infos = pl.infos
@@ -318,6 +351,10 @@ def bench_batch(args):
         _, per_plain = timed_each(lambda: solve(plain), args.plain_steps, stream)
         assert torch.equal(d_out, ref), "plain path differs from the batched solve"
         progress(f"plain: {statistics.median(per_plain):.1f} ms per solve")
+        solve(side)
+        _, per_side = timed_each(lambda: solve(side), args.eager_steps, stream)
+        assert torch.equal(d_out, ref), "batched solve on 4 streams differs"
+        progress(f"batched on 4 streams (eager): {statistics.median(per_side):.1f} ms")
         solve(timing)
         timing.stage_times()
         solve(timing)
@@ -326,6 +363,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     det_ms = stage_ms["determinants"]
     achieved = updates / (det_ms / 1e3) / 1e12
+    peak = alu_peak_updates([(i["n"], i["pn"] * i["G"]) for i in infos]) / 1e12
     ms_plain = statistics.median(per_plain)
     ms_med = statistics.median(per)
     line = {
@@ -348,16 +386,20 @@ def bench_batch(args):
         "plain_ms_per_step": ms_plain,
         "batched_over_plain": ms_plain / ms_med,
         "stage_ms_batched": stage_ms,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_UPDATES / 1e12,
-                     "unit": "T elimination-updates/s",
-                     "frac": achieved / (ALU_PEAK_UPDATES / 1e12), "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "T elimination-updates/s", "frac": achieved / peak,
+                     "frac_of_single_step_peak": achieved / (SINGLE_STEP_PEAK_UPDATES / 1e12),
+                     "traffic": None,
                      "kernel": "det_fused(_pair)_batch_kernel<n,lanes>: every elimination "
                                "launch of one batched solve",
                      "work_per_launch": updates, "avg_ms": det_ms,
                      "avg_ms_source": "HIP events before and after each elimination launch of "
                                       "one batched solve (sum)"},
         "plan_seconds": plan_s,
+        "batched_4_streams_eager_ms_median": statistics.median(per_side),
     }
+    progress("small-matrix subset")
+    line["small_subset"] = bench_small_subset(mats, args)
     progress("batch done; 12x12 trivariate roofline")
     c2, (arr2, info2) = config2_roofline()
     line["roofline_config2"] = c2
@@ -365,6 +407,68 @@ def bench_batch(args):
         progress("oracle on the host")
         line["cpu_baseline"] = cpu_baseline_batch(mats, infos, args.cpu_budget)
     print(json.dumps(line), flush=True)
+
+
+def plan_batch_streams(pdm, mats, streams):
+    """A batched plan whose elimination launches use `streams` streams (the library reads
+    POLYDET_BATCH_STREAMS when the plan is made)."""
+    old = os.environ.get("POLYDET_BATCH_STREAMS")
+    os.environ["POLYDET_BATCH_STREAMS"] = str(streams)
+    try:
+        return pdm.plan_batch(mats)
+    finally:
+        if old is None:
+            del os.environ["POLYDET_BATCH_STREAMS"]
+        else:
+            os.environ["POLYDET_BATCH_STREAMS"] = old
+
+
+def bench_small_subset(mats, args, max_n=12):
+    """Batched against plain on the matrices of order <= max_n alone (launch-bound work: few
+    determinants per matrix), both replayed from captured graphs, median of --steps solves."""
+    import numpy as np
+    import torch
+
+    import paper_2010_12117_amd as pdm
+    sub = [a for a in mats if a.shape[0] <= max_n]
+    pl = pdm.plan_batch(sub)
+    plain = pdm.plan_batch(sub, flags=pdm.BATCH_PLAIN)
+    co, oo = [], []
+    c = o = 0
+    for a, info in zip(sub, pl.infos):
+        co.append(c)
+        oo.append(o)
+        c += a.size
+        o += info["ncoeff"] * info["limbs"]
+    dev = torch.device("cuda:0")
+    d_coeffs = torch.from_numpy(np.concatenate([a.reshape(-1) for a in sub])).to(dev)
+    d_out = torch.empty(o, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(pl.infos[0]["workspace_bytes"], plain.infos[0]["workspace_bytes"]),
+                     dtype=torch.uint8, device=dev)
+    stream = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(stream):
+        for name, p in (("batched", pl), ("plain", plain)):
+            def solve(p=p):
+                pdm.solve_batch_device(p, d_coeffs, co, d_out, oo, workspace=ws, stream=stream)
+            for _ in range(2):
+                solve()
+            stream.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=stream):
+                solve()
+            _, per = timed_each(graph.replay, max(5, args.steps), stream)
+            res[name] = statistics.median(per)
+            if name == "batched":
+                ref = d_out.clone()
+            else:
+                assert torch.equal(d_out, ref), "plain differs from batched on the subset"
+    moddets = sum(i["pn"] * i["G"] for i in pl.infos)
+    return {"workload": f"the {len(sub)} matrices of order <= {max_n} of the batch",
+            "matrices": len(sub), "modular_dets": moddets,
+            "batched_ms_median": res["batched"], "plain_ms_median": res["plain"],
+            "batched_over_plain": res["plain"] / res["batched"],
+            "value_batched": moddets / (res["batched"] / 1e3)}
 
 
 def bench_single(args):
@@ -405,6 +509,7 @@ def bench_single(args):
     nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
     work = pn * G * det_updates(n)
     achieved = work / (stage["determinants"] / 1e3) / 1e12
+    peak = alu_peak_updates([(n, pn * G)]) / 1e12
     traffic = (DET_TRAFFIC["bytes"]
                if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
     eval_bytes = expand_bytes(pn, nnz, [x + 1 for x in deg], list(info["N"]))
@@ -421,11 +526,11 @@ def bench_single(args):
                    "nonzero_entries": nnz},
         "exact_dets_per_s": 1e3 / ms,
         "stage_kernel_ms": stage,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_UPDATES / 1e12,
-                     "unit": "T elimination-updates/s",
-                     "frac": achieved / (ALU_PEAK_UPDATES / 1e12), "traffic": traffic,
-                     "kernel": det_kernel_name(info), "work_per_launch": work,
-                     "avg_ms": stage["determinants"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "T elimination-updates/s", "frac": achieved / peak,
+                     "traffic": traffic, "kernel": det_kernel_name(info),
+                     "work_per_launch": work, "avg_ms": stage["determinants"],
+                     "frac_of_single_step_peak": achieved / (SINGLE_STEP_PEAK_UPDATES / 1e12)},
         "roofline_other": {"bound": "hbm", "achieved": eval_bytes / (stage["evaluate"] / 1e3) / 1e9,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": eval_bytes / (stage["evaluate"] / 1e3) / 1e9 / HBM_PEAK_GBS,
@@ -526,7 +631,8 @@ def calibrate_alu(args):
     lib.polydet_calibrate_alu.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
     lib.polydet_calibrate_alu.restype = ctypes.c_int
-    names = ["mad_u64_u32", "mul_lo_u32", "add_u32", "elimination_update", "fma_f64", "fma_f32"]
+    names = ["mad_u64_u32", "mul_lo_u32", "add_u32", "elimination_update", "fma_f64", "fma_f32",
+             "two_step_update", "update_64bit"]
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     out = {}
@@ -546,7 +652,8 @@ def calibrate_alu(args):
     mix = 1.0 / (3 / mad + 1 / mul + 1 / add)  # updates per clock per CU from the measured rates
     line = {"metric": "vector-ALU throughput probes", "unit": "ops/s", "probes": out,
             "blocks": args.probe_blocks, "iters_per_thread": args.probe_iters,
-            "update_peak_derived": ALU_PEAK_UPDATES,
+            "update_peak_derived": SINGLE_STEP_PEAK_UPDATES,
+            "two_step_update_peak_derived": CU * CLOCK_HZ / (5 * MULT_CLK + 2 * PLAIN_CLK),
             "update_peak_from_measured_instruction_rates": mix * CU * CLOCK_HZ,
             "update_measured": out["elimination_update"]["ops_per_s"],
             "clock_assumed_hz": CLOCK_HZ, "cus": CU}

@@ -31,7 +31,11 @@ typedef enum polydet_probe {
                               * kernels issue it: two products, one Montgomery reduction */
   POLYDET_PROBE_FMA_F64 = 4, /* v_fma_f64, the published fp64 vector rate */
   POLYDET_PROBE_FMA_F32 = 5, /* v_fma_f32 (unpacked) */
-  POLYDET_PROBE_COUNT = 6
+  POLYDET_PROBE_UPDATE2 = 6, /* one two-step elimination update a <- (D a + f1 u + f0 v) / 2^32
+                              * mod p, as the kernels issue it: three products, one reduction */
+  POLYDET_PROBE_UPDATE64 = 7, /* the single-step update with 64-bit residues (a prime below
+                               * 2^62, R = 2^64): two 64 x 64-bit products, one reduction */
+  POLYDET_PROBE_COUNT = 8
 } polydet_probe;
 
 /* Runs probe `probe` once and writes its rate to *ops_per_s. Synchronous: waits for the

@@ -14,6 +14,15 @@ namespace {
 constexpr int kProbeBlock = 256;
 constexpr int kChains = 8;
 
+// An odd modulus below 2^62 for the 64-bit probe (2^61 - 1, a Mersenne prime) and its
+// -q^{-1} mod 2^64 by Newton's iteration (each step doubles the correct low bits).
+constexpr uint64_t kProbePrime64 = (1ull << 61) - 1;
+__host__ __device__ constexpr uint64_t probe_qinv64() {
+  uint64_t inv = kProbePrime64;
+  for (int it = 0; it < 6; ++it) inv *= 2u - kProbePrime64 * inv;
+  return 0ull - inv;
+}
+
 template <int PROBE>
 __global__ __launch_bounds__(kProbeBlock) void probe_kernel(uint32_t* out, int iters,
                                                             uint32_t seed, uint32_t p,
@@ -54,6 +63,48 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(uint32_t* out, int i
     }
 #pragma unroll
     for (int c = 0; c < kChains; ++c) res ^= x[c];
+  } else if constexpr (PROBE == POLYDET_PROBE_UPDATE2) {
+    // a_c <- (D a_c + f1 b_{c+1} + f0 b_{c+2}) / R with b = a / 2 (below p): the kernels'
+    // two-step update (mm3_lazy) with both column factors changing every iteration, so that
+    // no product is loop-invariant; one shift per update comes on top of the kernels' mix
+    uint32_t a[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) a[c] = (seed + 7 * c + t) % p;
+    const uint32_t D = (seed * 13u + 1u) % p, f1 = (seed * 17u + 3u) % p;
+    const uint32_t f0 = (seed * 19u + 5u) % p;
+    for (int i = 0; i < iters; ++i) {
+      uint32_t b[kChains];
+#pragma unroll
+      for (int c = 0; c < kChains; ++c) b[c] = a[c] >> 1;
+#pragma unroll
+      for (int c = 0; c < kChains; ++c)
+        a[c] = pd::mm3_lazy(D, a[c], f1, b[(c + 1) % kChains], f0, b[(c + 2) % kChains], p, pinv);
+    }
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) res ^= a[c];
+  } else if constexpr (PROBE == POLYDET_PROBE_UPDATE64) {
+    // a_c <- (pi a_c + m a_{c+1}) / 2^64 mod q with q < 2^62 (Montgomery with R = 2^64): the
+    // 128-bit sum of two products, m = t mod 2^64 * (-q^-1), (t + m q) / 2^64 in [0, 2q)
+    const uint64_t q = kProbePrime64, qinv = probe_qinv64();
+    uint64_t a[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) a[c] = ((uint64_t)seed * (7 * c + 1) + t) % q;
+    const uint64_t piv = ((uint64_t)seed * 13u + 1u) % q, m = ((uint64_t)seed * 17u + 3u) % q;
+    for (int i = 0; i < iters; ++i) {
+      const uint64_t a0 = a[0];
+#pragma unroll
+      for (int c = 0; c < kChains; ++c) {
+        const uint64_t b = c + 1 < kChains ? a[c + 1] : a0;
+        const uint64_t l1 = piv * a[c], h1 = __umul64hi(piv, a[c]);
+        const uint64_t l2 = m * b, h2 = __umul64hi(m, b);
+        const uint64_t lo = l1 + l2;
+        const uint64_t hi = h1 + h2 + (lo < l1 ? 1u : 0u);
+        const uint64_t mm = lo * qinv;
+        a[c] = hi + __umul64hi(mm, q) + (lo != 0 ? 1u : 0u);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) res ^= (uint32_t)a[c] ^ (uint32_t)(a[c] >> 32);
   } else if constexpr (PROBE == POLYDET_PROBE_UPDATE) {
     // a_c <- (pi a_c + m a_{c+1}) / R: the second product's operand changes every iteration,
     // as the pivot row's entries do in the elimination, so nothing is loop-invariant
@@ -107,6 +158,9 @@ hipError_t launch(int probe, uint32_t* out, int blocks, int iters, hipStream_t s
     case POLYDET_PROBE_ADD: return launch_probe<POLYDET_PROBE_ADD>(out, blocks, iters, st);
     case POLYDET_PROBE_UPDATE: return launch_probe<POLYDET_PROBE_UPDATE>(out, blocks, iters, st);
     case POLYDET_PROBE_FMA_F64: return launch_probe<POLYDET_PROBE_FMA_F64>(out, blocks, iters, st);
+    case POLYDET_PROBE_UPDATE2: return launch_probe<POLYDET_PROBE_UPDATE2>(out, blocks, iters, st);
+    case POLYDET_PROBE_UPDATE64:
+      return launch_probe<POLYDET_PROBE_UPDATE64>(out, blocks, iters, st);
     default: return launch_probe<POLYDET_PROBE_FMA_F32>(out, blocks, iters, st);
   }
 }

@@ -133,11 +133,16 @@ def test_batch_across_chunks(monkeypatch):
         assert box_to_dict(got[i]) == box_to_dict(expect), i
 
 
-def test_batch_graph_replay():
-    # a captured batched solve replays bit-identically, with eager work between replays
+@pytest.mark.parametrize("streams", [1, 4])
+def test_batch_graph_replay(streams, monkeypatch):
+    # a captured batched solve replays bit-identically, with eager work between replays; with
+    # 4 streams the elimination launches fork from and join back into the captured stream
     import torch
     mats = mixed_batch(seed=1, count=24)
+    monkeypatch.setenv("POLYDET_BATCH_STREAMS", str(streams))
     pl = pdm.plan_batch(mats)
+    monkeypatch.delenv("POLYDET_BATCH_STREAMS")
+    ref = pdm.plan_batch(mats)
     d_coeffs, co, d_out, oo = pack(mats, pl)
     ws = torch.empty(pl.infos[0]["workspace_bytes"], dtype=torch.uint8, device="cuda")
     stream = torch.cuda.Stream()
@@ -145,6 +150,10 @@ def test_batch_graph_replay():
         pdm.solve_batch_device(pl, d_coeffs, co, d_out, oo, workspace=ws, stream=stream)
     stream.synchronize()
     eager = d_out.clone()
+    with torch.cuda.stream(stream):
+        pdm.solve_batch_device(ref, d_coeffs, co, d_out, oo, workspace=ws, stream=stream)
+    stream.synchronize()
+    assert torch.equal(d_out, eager)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
         pdm.solve_batch_device(pl, d_coeffs, co, d_out, oo, workspace=ws, stream=stream)
