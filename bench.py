@@ -62,19 +62,52 @@ def det_issue_clk(n: int) -> float:
     return clk
 
 
+def eval_issue_clk(m0: int) -> float:
+    """Minimal issue cost in CU-clocks per lane of evaluating one entry at one point along the
+    first variable (m0 coefficients), as the elimination kernel does before eliminating: with
+    2..4 coefficients the values at j and j + N/2 share the even and odd sums, so a point costs
+    one two-product reduction (3 mad + 1 mul_lo + a conditional subtraction) and one addition;
+    otherwise ceil(m0/2) such reductions and one modular addition (3 plain) between each."""
+    if m0 <= 1:
+        return 0.0
+    mm2 = 4 * MULT_CLK + 2 * PLAIN_CLK
+    if 2 <= m0 <= 4:
+        return mm2 + PLAIN_CLK
+    r = (m0 + 1) // 2
+    return r * mm2 + (r - 1) * 3 * PLAIN_CLK
+
+
 def alu_peak_updates(work):
     """Peak elimination-updates per second (the determinant's sum_{m<n} m^2 modular
-    multiply-subtracts, the algorithmic unit) of a mix of determinants, `work` = [(n, dets)]:
-    the chip issuing the kernels' minimal instruction mix on every CU every clock."""
-    upd = sum(d * det_updates(n) for n, d in work)
-    clk = sum(d * det_issue_clk(n) for n, d in work)
+    multiply-subtracts, the algorithmic unit) of the elimination launches of a mix of
+    determinants, `work` = [(n, dets, nonzero entries, m0)]: the chip issuing, on every CU
+    every clock, the launches' minimal instruction mix, which is the two-column elimination
+    and the evaluation of each nonzero entry along the first variable that the same kernel
+    does first."""
+    upd = sum(d * det_updates(n) for n, d, _, _ in work)
+    clk = sum(d * (det_issue_clk(n) + nnz * eval_issue_clk(m0)) for n, d, nnz, m0 in work)
     return upd / clk * CU * CLOCK_HZ if clk else 0.0
 
 
+def alu_peak_updates_elimination_only(work):
+    """The same peak with the elimination's instructions alone (no evaluation)."""
+    upd = sum(d * det_updates(n) for n, d, _, _ in work)
+    clk = sum(d * det_issue_clk(n) for n, d, _, _ in work)
+    return upd / clk * CU * CLOCK_HZ if clk else 0.0
+
+
+def nonzero_entries(a) -> int:
+    """Entries of a coefficient array [n][n][...] with a nonzero coefficient."""
+    import numpy as np
+    n = a.shape[0]
+    return int(np.count_nonzero(np.abs(a).reshape(n * n, -1).sum(axis=1)))
+
+
 # HBM bytes per launch of the 12 x 12 trivariate workload's elimination kernel, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB copy, valid only for the kernel sources
-# and tuning table they were taken with (their hash).
-DET_TRAFFIC = {"sources_sha256_16": "1809aef6fb7ee63f", "bytes": 186.2e6 + 14.7e6}
+# FETCH_SIZE (22,850 KiB) and WRITE_SIZE (14,336 KiB) passes, scaled by what the same counters
+# read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0), valid only for the kernel sources and
+# tuning table they were taken with (their hash).
+DET_TRAFFIC = {"sources_sha256_16": "388e0bde3ee0a621", "bytes": 46.80e6 + 14.68e6}
 
 STAGES = ("reduce", "evaluate", "determinants", "finalize", "interpolate", "reconstruct")
 
@@ -273,7 +306,8 @@ def config2_roofline(reps=50):
     nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
     work = pn * G * det_updates(n)
     achieved = work / (stage["determinants"] / 1e3) / 1e12
-    peak = alu_peak_updates([(n, pn * G)]) / 1e12
+    mix = [(n, pn * G, nnz, deg[0] + 1)]
+    peak = alu_peak_updates(mix) / 1e12
     traffic = (DET_TRAFFIC["bytes"]
                if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
     eval_bytes = expand_bytes(pn, nnz, [x + 1 for x in deg], list(info["N"]))
@@ -288,6 +322,7 @@ def config2_roofline(reps=50):
                      "unit": "T elimination-updates/s", "frac": achieved / peak,
                      "traffic": traffic, "kernel": det_kernel_name(info),
                      "work_per_launch": work, "avg_ms": stage["determinants"],
+                     "frac_elimination_only": achieved / (alu_peak_updates_elimination_only(mix) / 1e12),
                      "frac_of_single_step_peak": achieved / (SINGLE_STEP_PEAK_UPDATES / 1e12)},
         "evaluate_roofline": {"bound": "hbm", "bytes_per_solve": eval_bytes,
                               "achieved": eval_bytes / (stage["evaluate"] / 1e3) / 1e9,
@@ -308,7 +343,7 @@ def bench_batch(args):
     pl = pdm.plan_batch(mats)
     plan_s = time.perf_counter() - t0
     plain = pdm.plan_batch(mats, flags=pdm.BATCH_PLAIN)
-    side = plan_batch_streams(pdm, mats, 4)  # elimination launches side by side, 4 streams
+    side = None if args.no_extras else plan_batch_streams(pdm, mats, 4)  # side by side, 4 streams
     timing = pdm.plan_batch(mats, flags=pdm.STAGE_TIMING)
     progress(f"plans built ({plan_s:.1f} s for the batched one)")
     infos = pl.infos
@@ -344,17 +379,21 @@ def bench_batch(args):
         ms_graph = total / args.steps
         assert torch.equal(d_out, ref), "graph replay differs from the eager solve"
         progress(f"batched (graph): {ms_graph:.1f} ms per solve")
-        _, per_eager = timed_each(lambda: solve(pl), args.eager_steps, stream)
-        progress(f"batched (eager): {statistics.median(per_eager):.1f} ms per solve")
+        per_eager = [float("nan")]
+        if args.eager_steps > 0:
+            _, per_eager = timed_each(lambda: solve(pl), args.eager_steps, stream)
+            progress(f"batched (eager): {statistics.median(per_eager):.1f} ms per solve")
         for _ in range(args.warmup):
             solve(plain)
         _, per_plain = timed_each(lambda: solve(plain), args.plain_steps, stream)
         assert torch.equal(d_out, ref), "plain path differs from the batched solve"
         progress(f"plain: {statistics.median(per_plain):.1f} ms per solve")
-        solve(side)
-        _, per_side = timed_each(lambda: solve(side), args.eager_steps, stream)
-        assert torch.equal(d_out, ref), "batched solve on 4 streams differs"
-        progress(f"batched on 4 streams (eager): {statistics.median(per_side):.1f} ms")
+        per_side = [float("nan")]
+        if side is not None:
+            solve(side)
+            _, per_side = timed_each(lambda: solve(side), max(1, args.eager_steps), stream)
+            assert torch.equal(d_out, ref), "batched solve on 4 streams differs"
+            progress(f"batched on 4 streams (eager): {statistics.median(per_side):.1f} ms")
         solve(timing)
         timing.stage_times()
         solve(timing)
@@ -363,7 +402,9 @@ def bench_batch(args):
     torch.cuda.synchronize()
     det_ms = stage_ms["determinants"]
     achieved = updates / (det_ms / 1e3) / 1e12
-    peak = alu_peak_updates([(i["n"], i["pn"] * i["G"]) for i in infos]) / 1e12
+    mix = [(i["n"], i["pn"] * i["G"], nonzero_entries(a), (a.shape[2] if a.ndim > 2 else 1))
+           for a, i in zip(mats, infos)]
+    peak = alu_peak_updates(mix) / 1e12
     ms_plain = statistics.median(per_plain)
     ms_med = statistics.median(per)
     line = {
@@ -388,6 +429,7 @@ def bench_batch(args):
         "stage_ms_batched": stage_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "T elimination-updates/s", "frac": achieved / peak,
+                     "frac_elimination_only": achieved / (alu_peak_updates_elimination_only(mix) / 1e12),
                      "frac_of_single_step_peak": achieved / (SINGLE_STEP_PEAK_UPDATES / 1e12),
                      "traffic": None,
                      "kernel": "det_fused(_pair)_batch_kernel<n,lanes>: every elimination "
@@ -398,11 +440,13 @@ def bench_batch(args):
         "plan_seconds": plan_s,
         "batched_4_streams_eager_ms_median": statistics.median(per_side),
     }
-    progress("small-matrix subset")
-    line["small_subset"] = bench_small_subset(mats, args)
-    progress("batch done; 12x12 trivariate roofline")
-    c2, (arr2, info2) = config2_roofline()
-    line["roofline_config2"] = c2
+    if not args.no_extras:
+        progress("small-matrix subset")
+        line["small_subset"] = bench_small_subset(mats, args)
+    if not args.no_extras:
+        progress("batch done; 12x12 trivariate roofline")
+        c2, (arr2, info2) = config2_roofline()
+        line["roofline_config2"] = c2
     if not args.no_cpu_baseline:
         progress("oracle on the host")
         line["cpu_baseline"] = cpu_baseline_batch(mats, infos, args.cpu_budget)
@@ -509,7 +553,8 @@ def bench_single(args):
     nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
     work = pn * G * det_updates(n)
     achieved = work / (stage["determinants"] / 1e3) / 1e12
-    peak = alu_peak_updates([(n, pn * G)]) / 1e12
+    mix = [(n, pn * G, nnz, deg[0] + 1)]
+    peak = alu_peak_updates(mix) / 1e12
     traffic = (DET_TRAFFIC["bytes"]
                if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
     eval_bytes = expand_bytes(pn, nnz, [x + 1 for x in deg], list(info["N"]))
@@ -530,6 +575,7 @@ def bench_single(args):
                      "unit": "T elimination-updates/s", "frac": achieved / peak,
                      "traffic": traffic, "kernel": det_kernel_name(info),
                      "work_per_launch": work, "avg_ms": stage["determinants"],
+                     "frac_elimination_only": achieved / (alu_peak_updates_elimination_only(mix) / 1e12),
                      "frac_of_single_step_peak": achieved / (SINGLE_STEP_PEAK_UPDATES / 1e12)},
         "roofline_other": {"bound": "hbm", "achieved": eval_bytes / (stage["evaluate"] / 1e3) / 1e9,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -672,6 +718,9 @@ def main():
     ap.add_argument("--eager-steps", type=int, default=2,
                     help="timed eager (not graph-replayed) batched solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="batch workload: only the batched and plain solves and the stage-timed "
+                         "pass (no 4-stream, subset or single-matrix figures; for kernel traces)")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of the oracle on the host (batch workload)")
     ap.add_argument("--workload", default="config4", choices=["config4", "config2", "config5"],

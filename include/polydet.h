@@ -164,6 +164,9 @@ typedef struct polydet_plan_info {
                              * as in Sylvester matrices, are evaluated once); otherwise n*n */
   double predicted_ms;      /* predicted device time of polydet_solve on this plan, from the
                              * rates installed when the plan was built (polydet_set_rates) */
+  int32_t grid_slabs;       /* 1, or (capped plans where one prime does not fit) the number of
+                             * slabs of the grid along the second variable that S2 and S3 of
+                             * one prime run in turn (Section 2: the grid is cut evenly) */
 } polydet_plan_info;
 
 typedef struct polydet_plan_s* polydet_plan_t;
@@ -189,9 +192,14 @@ polydet_status polydet_plan(const polydet_shape* shape, const int64_t* host_coef
  * info.prime_group, the largest that fits: S1-S4 (reduce, evaluation, determinants,
  * interpolation) run group by group on the stream, each group leaving its coefficient
  * residues in the workspace, and the reconstruction runs once at the end (the paper solves
- * one prime at a time; Algorithm 1). Results are identical to the uncapped plan.
- * EUNSUPPORTED if even one prime does not fit; EINVAL with POLYDET_STAGE_TIMING when the cap
- * splits the primes. */
+ * one prime at a time; Algorithm 1). When even one prime does not fit, the plan also cuts
+ * each prime's grid into info.grid_slabs slabs along the second variable (the least number,
+ * a power of two, that fits; Section 2 cuts the grid evenly into chunks): the evaluation over
+ * that variable and the determinants run slab by slab, and only one slab's evaluated entries
+ * are held at a time. Results are identical to the uncapped plan. EUNSUPPORTED if one prime
+ * does not fit even in slabs (or the plan cannot be slabbed: fewer than two variables, or the
+ * unfused evaluation); EINVAL with POLYDET_STAGE_TIMING when the cap splits the primes or the
+ * grid. */
 polydet_status polydet_plan_capped(const polydet_shape* shape, const int64_t* host_coeffs,
                                    uint32_t flags, size_t max_workspace_bytes,
                                    polydet_plan_t* out);

@@ -66,7 +66,7 @@ class PlanInfo(ctypes.Structure):
                 ("row_order", ctypes.c_uint8 * 32), ("det_left_looking", ctypes.c_int32),
                 ("prime_group", ctypes.c_int32), ("coef_bytes", ctypes.c_size_t),
                 ("off_den", ctypes.c_size_t), ("nslots", ctypes.c_int64),
-                ("predicted_ms", ctypes.c_double)]
+                ("predicted_ms", ctypes.c_double), ("grid_slabs", ctypes.c_int32)]
 
 
 TUNE_ORDERS = 33

@@ -25,6 +25,10 @@ struct FusedDetArgs {
   int64_t nslot;         // slots per prime in the pre-tensor
   int pn;
   bool fixup;            // repair launch: recompute only the points with den = 0
+  // A slab of the grid (capped plans): the R points of the pre-tensor are the local points
+  // r < seg at global r + off1 and r >= seg at global r + off2, of Rout per first-variable
+  // value in detv / denv. The whole grid: Rout = seg = R, off1 = off2 = 0.
+  int64_t Rout, seg, off1, off2;
 };
 
 template <int N, int GL>

@@ -340,9 +340,16 @@ __device__ __forceinline__ void fill_tile(uint32_t* tile, const uint32_t* __rest
 // In a repair launch (fixup = true) a block recomputes only the points whose denominator an
 // earlier launch left at 0 (a zero pivot the left-looking kernel cannot exchange away).
 // Returns whether this block has such a point; every thread of the block gets the answer.
+// Where the local point r of a slab lies on the grid (FusedDetArgs: seg, off1, off2).
+__device__ __forceinline__ int64_t slab_point(int64_t r, int64_t seg, int64_t off1,
+                                              int64_t off2) {
+  return r + (r < seg ? off1 : off2);
+}
+
 __device__ __forceinline__ bool block_needs_fixup(const uint32_t* __restrict__ denv, int64_t R,
                                                   int N0, int NJ, int Q, int S, int64_t r0,
-                                                  int jbase, int prime) {
+                                                  int jbase, int prime, int64_t Rout,
+                                                  int64_t seg, int64_t off1, int64_t off2) {
   int any = 0;
   const int halves = N0 / NJ;  // 2 when the points j0 and j0 + N0/2 are taken in pairs
   const int pts = Q * S * halves;
@@ -350,7 +357,8 @@ __device__ __forceinline__ bool block_needs_fixup(const uint32_t* __restrict__ d
     const int q = idx % Q, jo = (idx / Q) % S, hh = idx / (Q * S);
     const int j0 = jbase + jo;
     if (r0 + q < R && j0 < NJ &&
-        denv[(int64_t)prime * N0 * R + (int64_t)(j0 + hh * NJ) * R + r0 + q] == 0u)
+        denv[(int64_t)prime * N0 * Rout + (int64_t)(j0 + hh * NJ) * Rout +
+             slab_point(r0 + q, seg, off1, off2)] == 0u)
       any = 1;
   }
   return __syncthreads_or(any) != 0;
@@ -376,7 +384,8 @@ __device__ __forceinline__ void det_fused_body(
     uint32_t* __restrict__ denv, int64_t R,
     int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
     const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
-    const int32_t* __restrict__ entry_slot, int64_t nslot, int prime, int64_t bx, bool fixup) {
+    const int32_t* __restrict__ entry_slot, int64_t nslot, int prime, int64_t bx, bool fixup,
+    int64_t Rout, int64_t seg, int64_t off1, int64_t off2) {
   constexpr int C = (N + GL - 1) / GL;
   constexpr int NE = N * N;
   constexpr int NCP = C * GL;  // tile columns per row, padded for the last lane slot
@@ -387,7 +396,8 @@ __device__ __forceinline__ void det_fused_body(
   const int jbase = (int)(bx / rtiles) * S;
   const uint32_t* src = pre + (int64_t)prime * nslot * m0 * R;
   const int NJ = PAIR ? N0 / 2 : N0;
-  if (fixup && !block_needs_fixup(denv, R, N0, NJ, Q, S, r0, jbase, prime)) return;
+  if (fixup && !block_needs_fixup(denv, R, N0, NJ, Q, S, r0, jbase, prime, Rout, seg, off1, off2))
+    return;
   fill_tile<N, NCP>(tile, src, R, m0, Q, r0, zero, entry_slot);
   // Structurally zero entries as a wave-uniform bit mask (one lane per matrix only): the
   // paired evaluation branches around them (scalar branches; their registers are set to 0).
@@ -503,12 +513,23 @@ __device__ __forceinline__ void det_fused_body(
       }
     }
     const DetFrac d = eliminate<N, GL>(a, p, pinv, one);
-    const int64_t o = (int64_t)prime * N0 * R + (int64_t)(j0 + half * NJ) * R + r0 + q;
+    const int64_t o = (int64_t)prime * N0 * Rout + (int64_t)(j0 + half * NJ) * Rout +
+                      slab_point(r0 + q, seg, off1, off2);
     if (valid && t == 0 && (!fixup || denv[o] == 0u)) {
       detv[o] = d.num;
       denv[o] = d.den;
     }
   }
+}
+
+// The hardware hands a launch's workgroups to the 8 XCDs of the chip in turn (linear id mod
+// 8), and each XCD has its own L2. Neighbouring tiles read neighbouring 32-byte pieces of the
+// same 128-byte lines of the pre-tensor, so tile t is given to the workgroup that makes
+// consecutive tiles run on one XCD: with x blocks per row of the grid (a multiple of 8),
+// block b takes tile (b mod 8) x/8 + b / 8. Other grids keep the identity.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  if (nb % 8 != 0) return b;
+  return (b % 8) * (nb / 8) + b / 8;
 }
 
 template <int N, int GL>
@@ -517,10 +538,12 @@ void det_fused_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
     int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
     const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
-    const int32_t* __restrict__ slot, int64_t nslot, bool fixup) {
+    const int32_t* __restrict__ slot, int64_t nslot, bool fixup, int64_t Rout, int64_t seg,
+    int64_t off1, int64_t off2) {
   extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
   det_fused_body<N, GL, false>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
-                               slot, nslot, blockIdx.y, blockIdx.x, fixup);
+                               slot, nslot, blockIdx.y, xcd_tile(blockIdx.x, gridDim.x), fixup,
+                               Rout, seg, off1, off2);
 }
 
 template <int N, int GL>
@@ -529,10 +552,12 @@ void det_fused_pair_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
     int64_t R, int N0, int m0, int Q, int S, const uint32_t* __restrict__ tw0, int64_t tw_stride,
     const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
-    const int32_t* __restrict__ slot, int64_t nslot, bool fixup) {
+    const int32_t* __restrict__ slot, int64_t nslot, bool fixup, int64_t Rout, int64_t seg,
+    int64_t off1, int64_t off2) {
   extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
   det_fused_body<N, GL, true>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
-                               slot, nslot, blockIdx.y, blockIdx.x, fixup);
+                              slot, nslot, blockIdx.y, xcd_tile(blockIdx.x, gridDim.x), fixup,
+                              Rout, seg, off1, off2);
 }
 
 // Batched form: blocks walk the virtual blocks of every matrix of this order in the launch;
@@ -542,8 +567,8 @@ __device__ __forceinline__ void det_fused_batch_body(uint32_t* tile, const BDet*
                                                      int ndesc, int64_t vblocks,
                                                      uint8_t* __restrict__ ws, bool fixup) {
   // One block per virtual block (no persistent loop: the loop's state costs registers that
-  // the elimination needs).
-  const int64_t vb = blockIdx.x;
+  // the elimination needs), consecutive virtual blocks on one XCD.
+  const int64_t vb = xcd_tile(blockIdx.x, gridDim.x);
   if (vb >= vblocks) return;
   const BDet& d = desc[find_desc(desc, ndesc, vb)];
   const int64_t local = vb - d.block0;
@@ -552,7 +577,8 @@ __device__ __forceinline__ void det_fused_batch_body(uint32_t* tile, const BDet*
   det_fused_body<N, GL, PAIR>(tile, (const uint32_t*)(ws + d.pre_off),
                               (uint32_t*)(ws + d.detv_off), (uint32_t*)(ws + d.den_off), d.R,
                               d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride, d.pc, d.zero, d.slot,
-                              d.nslot, prime, local - (int64_t)prime * per_prime, fixup);
+                              d.nslot, prime, local - (int64_t)prime * per_prime, fixup, d.R,
+                              d.R, 0, 0);
 }
 
 template <int N, int GL>
@@ -799,11 +825,11 @@ hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st) {
   if (fused_paired(f.m0))
     hipLaunchKernelGGL((det_fused_pair_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre,
                        f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs,
-                       f.zero, f.slot, f.nslot, f.fixup);
+                       f.zero, f.slot, f.nslot, f.fixup, f.Rout, f.seg, f.off1, f.off2);
   else
     hipLaunchKernelGGL((det_fused_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre, f.detv,
                        f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs, f.zero,
-                       f.slot, f.nslot, f.fixup);
+                       f.slot, f.nslot, f.fixup, f.Rout, f.seg, f.off1, f.off2);
   return hipGetLastError();
 }
 

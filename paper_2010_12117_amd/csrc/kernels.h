@@ -22,6 +22,12 @@ int64_t finalize_threads(int64_t G, int pn);  // threads of the det = num / den 
 hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st);
 hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st);
 hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st);       // numerators, denominators
+// Grid slabs (MatPlan::slabs > 1, fused plans with two or more variables): the passes over
+// variables k-1 .. 2 once, then for each slab b the pass over variable 1 for its points and
+// their determinants.
+hipError_t run_evaluate_upper(const MatPlan& P, uint8_t* ws, hipStream_t st);
+hipError_t run_evaluate_slab(const MatPlan& P, uint8_t* ws, int slab, hipStream_t st);
+hipError_t run_det_slab(const MatPlan& P, uint8_t* ws, int slab, hipStream_t st);
 // det = num / den: a launch of its own only without variables; otherwise run_interpolate's
 // first pass divides as it loads
 hipError_t run_finalize(const MatPlan& P, uint8_t* ws, hipStream_t st);

@@ -93,14 +93,18 @@ __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
 // r and so j, the prime and the entry; they are taken from the wave's first index, which lets
 // the twiddle, constant and zero-flag loads be scalar.
 // ------------------------------------------------------------------------------------
+//
+// A slab of the grid (capped plans, one prime's pass over variable 1 in parts): the output
+// holds Nout < Nv values per line, the points jbase + j and, paired, jbase + j + Nv/2 for
+// j in [0, Nout/2), stored at j and j + Nout/2. jbase = 0 and Nout = Nv give the whole line.
 template <int M, bool UJ, bool EXACT>
 __device__ __forceinline__ void expand_body(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t idx, int64_t B,
     int64_t outer, int m, int Nv, int JC, int64_t inner, int64_t nent,
     const uint32_t* __restrict__ tw, int64_t tw_stride, const PrimeConst* __restrict__ pcs,
-    const uint8_t* __restrict__ zero, bool write_zero) {
+    const uint8_t* __restrict__ zero, bool write_zero, int jbase, int Nout) {
   const bool paired = expand_paired(Nv, m);
-  const int NJ = paired ? Nv / 2 : Nv;
+  const int NJ = paired ? Nout / 2 : Nout;
   const int nJB = NJ / JC;
   if (idx >= B * outer * nJB * inner) return;
   // inner and nJB are powers of two
@@ -119,7 +123,7 @@ __device__ __forceinline__ void expand_body(
   const int64_t b = bo / outer;
   const int prime = (int)(b / nent);
   const int64_t entry = b - (int64_t)prime * nent;
-  uint32_t* dst = out + bo * Nv * inner + q;
+  uint32_t* dst = out + bo * Nout * inner + q;
   const int j0 = jb * JC;
   if (zero && zero[entry]) {
     if (write_zero) {
@@ -145,23 +149,24 @@ __device__ __forceinline__ void expand_body(
       // With EXACT (m == M) the loop over e has no runtime condition, and the twiddle loads
       // of the unrolled points are issued together. Otherwise the terms past m - 1 (x[e] = 0,
       // adding nothing) are skipped.
+      const int jg = jbase + j;  // the point's index on the whole line
       uint32_t E = x[0], O = 0u;
 #pragma unroll
       for (int e = 2; e < M; e += 4) {
         if (EXACT || e < m) {
           if (e + 2 < M && (EXACT || e + 2 < m))
-            E = addm(E, mm2(x[e], w[(e * j) & mask], x[e + 2], w[((e + 2) * j) & mask], p, pinv), p);
+            E = addm(E, mm2(x[e], w[(e * jg) & mask], x[e + 2], w[((e + 2) * jg) & mask], p, pinv), p);
           else
-            E = addm(E, mm(x[e], w[(e * j) & mask], p, pinv), p);
+            E = addm(E, mm(x[e], w[(e * jg) & mask], p, pinv), p);
         }
       }
 #pragma unroll
       for (int e = 1; e < M; e += 4) {
         if (EXACT || e < m) {
           if (e + 2 < M && (EXACT || e + 2 < m))
-            O = addm(O, mm2(x[e], w[(e * j) & mask], x[e + 2], w[((e + 2) * j) & mask], p, pinv), p);
+            O = addm(O, mm2(x[e], w[(e * jg) & mask], x[e + 2], w[((e + 2) * jg) & mask], p, pinv), p);
           else
-            O = addm(O, mm(x[e], w[(e * j) & mask], p, pinv), p);
+            O = addm(O, mm(x[e], w[(e * jg) & mask], p, pinv), p);
         }
       }
       dst[(int64_t)j * inner] = addm(E, O, p);
@@ -178,11 +183,11 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t B, int64_t outer,
     int m, int Nv, int JC, int64_t inner, int64_t nent, const uint32_t* __restrict__ tw,
     int64_t tw_stride, const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
-    bool write_zero) {
+    bool write_zero, int jbase, int Nout) {
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   // the single-matrix launches pick M = m up to 8 (launch_expand)
   expand_body<M, UJ, (M <= 8)>(in, out, idx, B, outer, m, Nv, JC, inner, nent, tw, tw_stride, pcs, zero,
-                     write_zero);
+                     write_zero, jbase, Nout);
 }
 
 __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __restrict__ desc,
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __r
     const int64_t idx = (vb - d.block0) * kBlock + threadIdx.x;
     expand_body<kBatchMaxM, false, false>((const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), idx,
                             d.B, d.outer, d.m, d.Nv, d.JC, d.inner, d.nent, d.tw, d.tw_stride,
-                            d.pc, d.zero, false);
+                            d.pc, d.zero, false, 0, d.Nv);
   }
 }
 
@@ -555,53 +560,89 @@ __global__ __launch_bounds__(kBlock) void garner_batch_kernel(
 // ------------------------------------------------------------------------------------
 template <int M>
 hipError_t launch_expand_m(const MatPlan& P, const uint32_t* in, uint32_t* out, int64_t outer,
-                           int v, int64_t inner, hipStream_t st) {
+                           int v, int64_t inner, int jbase, int Nout, hipStream_t st) {
   const int64_t B = (int64_t)P.pn * P.nslot;
   if (B == 0) return hipSuccess;  // every entry is zero
-  const int JC = expand_outputs_per_thread(P.N[v], inner, P.m[v]);
-  const int64_t work = B * outer * (expand_jrange(P.N[v], P.m[v]) / JC) * inner;
+  const int JC = expand_outputs_per_thread(Nout, inner, P.m[v]);
+  const int64_t work = B * outer * (expand_jrange(Nout, P.m[v]) / JC) * inner;
   // the full evaluation tensor (last pass of the unfused path) is read without zero flags
   const bool write_zero = v == 0;
   if (inner >= 64)
     hipLaunchKernelGGL((expand_kernel<M, true>), dim3(blocks_for(work)), dim3(kBlock), 0, st, in,
                        out, B, outer, P.m[v], P.N[v], JC, inner, P.nslot, P.d_tw + P.tw_off[v],
-                       P.tw_stride, P.d_pc, P.d_slot_zero, write_zero);
+                       P.tw_stride, P.d_pc, P.d_slot_zero, write_zero, jbase, Nout);
   else
     hipLaunchKernelGGL((expand_kernel<M, false>), dim3(blocks_for(work)), dim3(kBlock), 0, st, in,
                        out, B, outer, P.m[v], P.N[v], JC, inner, P.nslot, P.d_tw + P.tw_off[v],
-                       P.tw_stride, P.d_pc, P.d_slot_zero, write_zero);
+                       P.tw_stride, P.d_pc, P.d_slot_zero, write_zero, jbase, Nout);
   return hipGetLastError();
 }
 
+// The pass over variable v; with jbase, Nout a slab of its grid (expand_body).
 hipError_t launch_expand(const MatPlan& P, const uint32_t* in, uint32_t* out, int64_t outer,
-                         int v, int64_t inner, hipStream_t st) {
+                         int v, int64_t inner, hipStream_t st, int jbase = 0, int Nout = 0) {
   const int m = P.m[v];
+  if (Nout == 0) Nout = P.N[v];
   switch (m) {
-    case 1: return launch_expand_m<1>(P, in, out, outer, v, inner, st);
-    case 2: return launch_expand_m<2>(P, in, out, outer, v, inner, st);
-    case 3: return launch_expand_m<3>(P, in, out, outer, v, inner, st);
-    case 4: return launch_expand_m<4>(P, in, out, outer, v, inner, st);
-    case 5: return launch_expand_m<5>(P, in, out, outer, v, inner, st);
-    case 6: return launch_expand_m<6>(P, in, out, outer, v, inner, st);
-    case 7: return launch_expand_m<7>(P, in, out, outer, v, inner, st);
-    case 8: return launch_expand_m<8>(P, in, out, outer, v, inner, st);
+    case 1: return launch_expand_m<1>(P, in, out, outer, v, inner, jbase, Nout, st);
+    case 2: return launch_expand_m<2>(P, in, out, outer, v, inner, jbase, Nout, st);
+    case 3: return launch_expand_m<3>(P, in, out, outer, v, inner, jbase, Nout, st);
+    case 4: return launch_expand_m<4>(P, in, out, outer, v, inner, jbase, Nout, st);
+    case 5: return launch_expand_m<5>(P, in, out, outer, v, inner, jbase, Nout, st);
+    case 6: return launch_expand_m<6>(P, in, out, outer, v, inner, jbase, Nout, st);
+    case 7: return launch_expand_m<7>(P, in, out, outer, v, inner, jbase, Nout, st);
+    case 8: return launch_expand_m<8>(P, in, out, outer, v, inner, jbase, Nout, st);
     default:
-      if (m <= 16) return launch_expand_m<16>(P, in, out, outer, v, inner, st);
-      return launch_expand_m<32>(P, in, out, outer, v, inner, st);
+      if (m <= 16) return launch_expand_m<16>(P, in, out, outer, v, inner, jbase, Nout, st);
+      return launch_expand_m<32>(P, in, out, outer, v, inner, jbase, Nout, st);
   }
 }
 
+// The points of slab b (of P.slabs) along variable 1: h = N_1 / (2 slabs) values j_1 from
+// b h and as many from N_1 / 2 + b h, whose pass over variable 1 is paired (expand_body).
+struct SlabMap {
+  int jbase, Nout;                // that pass's output: Nout = 2h values per line from jbase
+  int64_t R, seg, off1, off2;     // the elimination's local points (FusedDetArgs)
+};
+
+SlabMap slab_map(const MatPlan& P, int b) {
+  const int64_t R = P.G / P.N[0];
+  SlabMap s;
+  if (b < 0 || P.slabs <= 1) {
+    s.jbase = 0;
+    s.Nout = P.k >= 2 ? P.N[1] : 1;
+    s.R = s.seg = R;
+    s.off1 = s.off2 = 0;
+    return s;
+  }
+  const int64_t R1 = R / P.N[1];  // points of the variables after the first two
+  const int h = P.N[1] / (2 * P.slabs);
+  s.jbase = b * h;
+  s.Nout = 2 * h;
+  s.R = 2 * h * R1;
+  s.seg = h * R1;
+  s.off1 = (int64_t)b * h * R1;
+  s.off2 = ((int64_t)P.N[1] / 2 + (int64_t)b * h - h) * R1;
+  return s;
+}
+
 template <int N, int GL>
-hipError_t launch_det_ng(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hipStream_t st) {
+hipError_t launch_det_ng(const MatPlan& P, const uint8_t* ws, uint32_t* detv, int slab,
+                         hipStream_t st) {
   uint32_t* denv = (uint32_t*)(const_cast<uint8_t*>(ws) + P.off_den);
   if (!P.fused) {
     return det_launch<N, GL>((const uint32_t*)(ws + P.off_eval), detv, denv, P.G, P.pn, P.d_pc, st);
   }
+  const SlabMap sm = slab_map(P, slab);
   FusedDetArgs f;
   f.pre = (const uint32_t*)(ws + P.off_pre);
   f.detv = detv;
   f.denv = denv;
-  f.R = P.G / P.N[0];
+  f.R = sm.R;
+  f.Rout = P.G / P.N[0];
+  f.seg = sm.seg;
+  f.off1 = sm.off1;
+  f.off2 = sm.off2;
   f.N0 = P.N[0];
   f.m0 = P.m[0];
   f.Q = P.fuse_Q;
@@ -627,8 +668,9 @@ hipError_t launch_det_ng(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hi
 
 template <int N, int GL>
 struct SingleDet {
-  static hipError_t run(const MatPlan& P, const uint8_t* ws, uint32_t* detv, hipStream_t st) {
-    return launch_det_ng<N, GL>(P, ws, detv, st);
+  static hipError_t run(const MatPlan& P, const uint8_t* ws, uint32_t* detv, int slab,
+                        hipStream_t st) {
+    return launch_det_ng<N, GL>(P, ws, detv, slab, st);
   }
 };
 
@@ -736,8 +778,11 @@ hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipS
   return hipGetLastError();
 }
 
-hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
-  if (P.k == 0) return hipSuccess;  // the residues are the values at the single point
+// The evaluation passes over the variables v with vlo <= v <= vhi, from the last variable
+// down (passes alternate tmpA, tmpB); with slab >= 0 the pass over variable 1 makes that slab
+// only.
+hipError_t run_evaluate_passes(const MatPlan& P, uint8_t* ws, int vlo, int vhi, int slab,
+                               hipStream_t st) {
   const uint32_t* in = (const uint32_t*)(ws + P.off_res);
   uint32_t* bufs[2] = {(uint32_t*)(ws + P.off_tmpA), (uint32_t*)(ws + P.off_tmpB)};
   int which = 0;
@@ -747,12 +792,30 @@ hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
     for (int u = 0; u < v; ++u) outer *= P.m[u];
     for (int u = v + 1; u < P.k; ++u) inner *= P.N[u];
     uint32_t* out = v == 0 ? (uint32_t*)(ws + P.off_eval) : bufs[which];
-    hipError_t err = launch_expand(P, in, out, outer, v, inner, st);
-    if (err != hipSuccess) return err;
+    if (v >= vlo && v <= vhi) {
+      const SlabMap sm = slab_map(P, v == 1 ? slab : -1);
+      hipError_t err = v == 1 && slab >= 0
+                           ? launch_expand(P, in, out, outer, v, inner, st, sm.jbase, sm.Nout)
+                           : launch_expand(P, in, out, outer, v, inner, st);
+      if (err != hipSuccess) return err;
+    }
     in = out;
     which ^= 1;
   }
   return hipSuccess;
+}
+
+hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
+  if (P.k == 0) return hipSuccess;  // the residues are the values at the single point
+  return run_evaluate_passes(P, ws, 0, P.k - 1, -1, st);
+}
+
+hipError_t run_evaluate_upper(const MatPlan& P, uint8_t* ws, hipStream_t st) {
+  return run_evaluate_passes(P, ws, 2, P.k - 1, -1, st);  // variable 1 goes slab by slab
+}
+
+hipError_t run_evaluate_slab(const MatPlan& P, uint8_t* ws, int slab, hipStream_t st) {
+  return run_evaluate_passes(P, ws, 1, 1, slab, st);
 }
 
 int64_t finalize_threads(int64_t G, int pn) {
@@ -761,7 +824,12 @@ int64_t finalize_threads(int64_t G, int pn) {
 
 hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st) {
   return det_dispatch<SingleDet>(P.n, P.det_lanes, P, (const uint8_t*)ws,
-                                 (uint32_t*)(ws + P.off_detv), st);
+                                 (uint32_t*)(ws + P.off_detv), -1, st);
+}
+
+hipError_t run_det_slab(const MatPlan& P, uint8_t* ws, int slab, hipStream_t st) {
+  return det_dispatch<SingleDet>(P.n, P.det_lanes, P, (const uint8_t*)ws,
+                                 (uint32_t*)(ws + P.off_detv), slab, st);
 }
 
 hipError_t run_finalize(const MatPlan& P, uint8_t* ws, hipStream_t st) {

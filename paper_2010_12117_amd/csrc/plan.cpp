@@ -347,7 +347,8 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   // Workspace layout for pg primes at a time: every per-prime region holds pg primes, the
   // coefficient residues (S4's output, S5's input) all pn. pg < pn only when the caller caps
   // the workspace (max_ws): S1-S4 then run group by group.
-  auto layout = [&](size_t pg) -> size_t {
+  auto layout = [&](size_t pg, int slabs) -> size_t {
+  P.slabs = slabs;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -362,6 +363,7 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
     int64_t sz = 1;
     for (int u = 0; u < v; ++u) sz *= P.m[u];
     for (int u = v; u < s.k; ++u) sz *= P.N[u];
+    if (v == 1) sz /= slabs;  // one slab of the pre-tensor at a time
     const int which = (s.k - 1 - v) % 2;
     interAB[which] = std::max(interAB[which], (size_t)sz);
   }
@@ -373,7 +375,7 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   P.fused = s.k >= 1 && !(flags & 1u);
   if (P.fused) {
     constexpr size_t kFuseLds = 64 * 1024;
-    const int64_t R = P.G / P.N[0];
+    const int64_t R = P.G / P.N[0] / slabs;  // points of the pre-tensor (one slab)
     const int per_block = fused_slots(256, P.det_lanes, P.m[0]);
     const int NJ = fused_jrange(P.N[0], P.m[0]);
     int Q = tune.tile_points[tclass][P.n] > 0 ? tune.tile_points[tclass][P.n] : 16;
@@ -403,7 +405,7 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   // (flag bit 2) up to kLLMaxN, or where the table chose it; the exchanging kernel alone by
   // default and with flag bit 3.
   const bool want_ll = (flags & 4u) || (!(flags & 8u) && tune.left_looking[tclass][P.n] == 1);
-  P.det_ll = P.fused && want_ll && !(flags & 8u) && s.n <= kLLMaxN;
+  P.det_ll = P.fused && want_ll && !(flags & 8u) && s.n <= kLLMaxN && slabs == 1;
   if (P.fused) {
     // the pre-tensor is the output of the evaluation pass over variable 1 (pass index
     // k - 2 counting from the last variable; passes alternate tmpA, tmpB), or the residues
@@ -428,18 +430,30 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
   return std::max<size_t>(off, 256);
   };
   P.prime_group = P.pn;
-  P.ws_bytes = layout(P.pn);
+  P.ws_bytes = layout(P.pn, 1);
   if (max_ws > 0 && P.ws_bytes > max_ws) {
     // the largest group of primes whose solve fits (integer matrices are never split: their
     // one point per prime costs nothing)
     int g = s.k == 0 ? 0 : P.pn - 1;
-    while (g >= 1 && layout(g) > max_ws) --g;
-    if (g < 1) {
-      *unsupported = true;
-      return "the workspace cap is below the footprint of a solve one prime at a time";
+    while (g >= 1 && layout(g, 1) > max_ws) --g;
+    if (g >= 1) {
+      P.prime_group = g;
+      P.ws_bytes = layout(g, 1);
+    } else {
+      // one prime at a time does not fit either: cut its grid into slabs along variable 1
+      // (fused plans with two or more variables; a slab holds at least one pair of values)
+      int sl = 2;
+      const bool can = P.fused && s.k >= 2 && P.N[1] >= 4;
+      while (can && sl < P.N[1] / 2 && layout(1, sl) > max_ws) sl *= 2;
+      if (!can || layout(1, sl) > max_ws || !P.fused) {
+        *unsupported = true;
+        return can ? "the workspace cap is below the footprint of a solve one prime at a time, "
+                     "even with its grid in slabs"
+                   : "the workspace cap is below the footprint of a solve one prime at a time";
+      }
+      P.prime_group = 1;
+      P.ws_bytes = layout(1, sl);
     }
-    P.prime_group = g;
-    P.ws_bytes = layout(g);
   }
   P.in_bytes = (size_t)P.nent * P.T * 8;
   P.out_bytes = (size_t)P.C * P.L * 4;

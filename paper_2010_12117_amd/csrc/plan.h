@@ -84,6 +84,10 @@ struct MatPlan {
   int64_t G = 1, C = 1, T = 1, nent = 0;
   int pn = 0, L = 0, prime_off = 0, det_lanes = 1;
   int prime_group = 0;  // primes per S1-S4 pass (pn unless the workspace is capped)
+  // Slabs of the grid along variable 1 (capped plans whose single prime does not fit): the
+  // pass over variable 1 and the elimination run slab by slab on a pre-tensor of R / slabs
+  // points; the determinants still fill the whole grid. 1 = the whole grid at once.
+  int slabs = 1;
   std::vector<uint32_t> primes;
   std::vector<PrimeConst> pc;
   std::vector<uint8_t> entry_zero;  // empty when the plan was built without coefficients

@@ -168,7 +168,7 @@ polydet_status make_plan(const polydet_shape* shapes, int32_t count,
     const int64_t* hc = host_coeffs ? host_coeffs[i] : nullptr;
     std::string err = pd::build_matplan(s, hc, flags, max_ws, &h->plan.mats[i], &unsupported);
     if (err.empty() && (flags & POLYDET_STAGE_TIMING) &&
-        h->plan.mats[i].prime_group < h->plan.mats[i].pn)
+        (h->plan.mats[i].prime_group < h->plan.mats[i].pn || h->plan.mats[i].slabs > 1))
       err = "stage timing needs a plan that solves all primes at once (no workspace cap)";
     if (err.empty() && !pd::det_config_supported(s.n, h->plan.mats[i].det_lanes)) {
       unsupported = true;
@@ -282,8 +282,20 @@ polydet_status run_primes(const pd::MatPlan& P, const int64_t* d_coeffs, int b, 
   for (int lo = b; lo < e; lo += g) {
     const pd::MatPlan R = pd::prime_range_plan(P, lo, std::min(e, lo + g));
     if ((err = pd::run_reduce(R, d_coeffs, ws, st)) != hipSuccess) return hip_fail(err, "reduce");
-    if ((err = pd::run_evaluate(R, ws, st)) != hipSuccess) return hip_fail(err, "evaluate");
-    if ((err = pd::run_det(R, ws, st)) != hipSuccess) return hip_fail(err, "determinants");
+    if (R.slabs > 1) {
+      // one prime's grid in slabs along variable 1: the pre-tensor holds one slab at a time,
+      // the determinants fill the whole grid
+      if ((err = pd::run_evaluate_upper(R, ws, st)) != hipSuccess) return hip_fail(err, "evaluate");
+      for (int b = 0; b < R.slabs; ++b) {
+        if ((err = pd::run_evaluate_slab(R, ws, b, st)) != hipSuccess)
+          return hip_fail(err, "evaluate");
+        if ((err = pd::run_det_slab(R, ws, b, st)) != hipSuccess)
+          return hip_fail(err, "determinants");
+      }
+    } else {
+      if ((err = pd::run_evaluate(R, ws, st)) != hipSuccess) return hip_fail(err, "evaluate");
+      if ((err = pd::run_det(R, ws, st)) != hipSuccess) return hip_fail(err, "determinants");
+    }
     if ((err = pd::run_finalize(R, ws, st)) != hipSuccess) return hip_fail(err, "finalize");
     if ((err = pd::run_interpolate(R, ws, st)) != hipSuccess) return hip_fail(err, "interpolate");
   }
@@ -337,7 +349,7 @@ polydet_status run_stages(const pd::MatPlan& P, int b, int e, const int64_t* d_c
 
 polydet_status run_one(const pd::MatPlan& P, const int64_t* d_coeffs, uint32_t* d_out,
                        uint8_t* ws, hipStream_t st, StageTimer* T) {
-  if (P.prime_group < P.pn) {  // capped workspace: S1-S4 by prime groups, then S5
+  if (P.prime_group < P.pn || P.slabs > 1) {  // capped: S1-S4 by prime groups (and slabs), S5
     polydet_status s = run_primes(P, d_coeffs, 0, P.pn, ws, st);
     if (s != POLYDET_OK) return s;
     hipError_t e = pd::run_reconstruct(P, ws, d_out, st);
@@ -405,6 +417,7 @@ polydet_status polydet_plan_query(polydet_plan_t plan, int32_t index, polydet_pl
   for (int i = 0; i < P.n && i < 32; ++i) out->row_order[i] = (uint8_t)P.row_order[i];
   out->det_left_looking = P.det_ll ? 1 : 0;
   out->prime_group = P.prime_group;
+  out->grid_slabs = P.slabs;
   out->coef_bytes = (size_t)P.pn * P.C * 4;
   out->in_bytes = P.in_bytes;
   out->out_bytes = P.out_bytes;
@@ -452,7 +465,7 @@ polydet_status polydet_solve_stages(polydet_plan_t plan, int32_t stage_begin, in
   if (stage_begin == 0 && !d_coeffs) return fail(POLYDET_EINVAL, "NULL coefficients");
   if (stage_end == POLYDET_NUM_STAGES && !d_out) return fail(POLYDET_EINVAL, "NULL output");
   const pd::MatPlan& P = plan->plan.mats[0];
-  if (P.prime_group < P.pn)
+  if (P.prime_group < P.pn || P.slabs > 1)
     return fail(POLYDET_EINVAL, "a capped plan runs by prime ranges (polydet_solve_primes)");
   if (workspace_bytes < P.ws_bytes) return fail(POLYDET_EINVAL, "workspace too small");
   if (((uintptr_t)d_workspace & 255) != 0) return fail(POLYDET_EINVAL, "workspace must be 256-byte aligned");

@@ -16,7 +16,8 @@ precedence over every job that has not, oldest first: short jobs stay ahead of l
 and long ones are not starved. In both policies the first job in that order that does not fit
 reserves its memory, and later jobs may start only if they fit beside the reservation. A job
 whose one-shot footprint exceeds the whole budget runs on a capped plan (polydet_plan_capped:
-primes in groups, same result) when one prime's footprint fits.
+primes in groups, and below one prime's footprint each prime's grid in slabs; same result)
+when that fits.
 
 With `prime_chunk`, a job runs as a sequence of prime ranges (polydet_solve_primes), one range
 in flight at a time, then the reconstruction (polydet_reconstruct). Between ranges the server
@@ -184,10 +185,10 @@ class Server:
         info = pl.info
         footprint = int(info["in_bytes"] + info["workspace_bytes"] + info["out_bytes"])
         if footprint > self.budget:
-            # primes in groups: the workspace shrinks to what the budget leaves
+            # primes in groups (and grid slabs): the workspace shrinks to what the budget leaves
             cap = self.budget - info["in_bytes"] - info["out_bytes"]
             too_big = ValueError(f"job needs {footprint} device bytes one-shot and does not fit "
-                                 "the server budget even one prime at a time")
+                                 "the server budget even one prime at a time in grid slabs")
             if cap <= 0:
                 raise too_big
             try:

@@ -120,6 +120,17 @@ def test_job_above_budget_runs_on_a_capped_plan():
     assert np.array_equal(r.limbs, alone(a))
 
 
+def test_job_above_one_prime_runs_on_grid_slabs():
+    # a budget below one prime's footprint: the job's grid runs in slabs, same result
+    a = W.config2()
+    info = pdm.plan(12, (3, 3, 3), host_coeffs=a, flags=pdm.HOST_ONLY).info
+    srv = S.Server(memory_budget=info["in_bytes"] + info["out_bytes"] + (7 << 20), slots=1)
+    r = srv.submit(a).result(timeout=120)
+    srv.close()
+    assert r.info["prime_group"] == 1 and r.info["grid_slabs"] >= 2
+    assert np.array_equal(r.limbs, alone(a))
+
+
 def test_config5_mix_with_a_large_job_equals_alone():
     # jobs drawn like the serving workload's (n 4..32, 2-3 variables, degree 1-5, coefficients
     # in [-2^16, 2^16]) plus one 32 x 32 trivariate degree-5 job, four at a time: every result

@@ -116,3 +116,76 @@ def test_integer_matrix_by_primes():
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), want)
     assert int(B.limbs_to_ints(out.cpu().numpy())[0]) == OD.det_bareiss_int(a.tolist())
+
+
+def capped_solve(arr, cap):
+    import torch
+    n, deg = B.shape_of(arr)
+    pl = pdm.plan(n, deg, host_coeffs=arr, max_workspace=cap)
+    out, ws = pdm.solve_device(pl, torch.from_numpy(np.ascontiguousarray(arr)).cuda())
+    torch.cuda.synchronize()
+    assert ws.numel() <= cap
+    return out.cpu().numpy(), pl
+
+
+@pytest.mark.parametrize("cap_mb", [9, 7, 6, 5.5])
+def test_grid_slabs_match_one_shot(cap_mb):
+    # a cap below one prime's footprint (11.8 MB): each prime's grid runs in 2 .. 16 slabs
+    # along the second variable, bit-identical to the one-shot solve
+    arr = W.config2()
+    want, _ = one_shot(arr)
+    got, pl = capped_solve(arr, int(cap_mb * (1 << 20)))
+    print(f"cap {cap_mb} MB: {pl.info['grid_slabs']} slabs", flush=True)
+    assert pl.info["prime_group"] == 1 and pl.info["grid_slabs"] >= 2
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("deg", [(5, 3), (2, 4, 1, 2), (3, 5, 2)])
+def test_grid_slabs_other_shapes_against_oracle(deg):
+    # two variables (the sliced pass reads the residues), four variables (two passes before
+    # it), and an unpaired first variable (6 coefficients); half the smallest one-prime
+    # footprint forces the most slabs that fit
+    import torch
+    rng = np.random.default_rng(90 + len(deg))
+    arr = W.random_matrix(rng, 4, deg, -50, 50, zero_prob=0.2)
+    n, _ = B.shape_of(arr)
+    want, full = one_shot(arr)
+    cap, info = full.info["workspace_bytes"], None
+    while True:
+        try:
+            info = pdm.plan(n, deg, host_coeffs=arr, flags=pdm.HOST_ONLY,
+                            max_workspace=cap).info
+        except pdm.PolydetError:
+            break
+        if info["grid_slabs"] >= 4:
+            break
+        cap = int(cap * 0.8)
+    got, pl = capped_solve(arr, max(cap, info["workspace_bytes"]))
+    print(f"deg {deg}: {pl.info['grid_slabs']} slabs", flush=True)
+    assert pl.info["grid_slabs"] >= 2
+    assert np.array_equal(got, want)
+    vals = B.limbs_to_ints(got)
+    box = np.empty(len(vals), dtype=object)
+    box[:] = vals
+    box = box.reshape(tuple(d + 1 for d in pl.info["D"]))
+    expect = OD.det_pointwise(arr, PL.det_degree_bound_from_shape(n, deg))
+    assert box_to_dict(box) == box_to_dict(expect)
+
+
+def test_grid_slabs_by_prime_ranges_and_resume():
+    # prime ranges on a slabbed plan, with the coefficient region carried to a fresh workspace
+    import torch
+    arr = W.config2()
+    want, _ = one_shot(arr)
+    pl = pdm.plan(12, (3, 3, 3), host_coeffs=arr, max_workspace=6 << 20)
+    assert pl.info["grid_slabs"] >= 4
+    d = torch.from_numpy(arr).cuda()
+    ws = torch.empty(pl.info["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    pdm.solve_primes_device(pl, d, 0, 3, ws)
+    saved = pdm.coefficient_region(pl, ws).clone()
+    ws2 = torch.full_like(ws, 0x5C)
+    pdm.coefficient_region(pl, ws2).copy_(saved)
+    pdm.solve_primes_device(pl, d, 3, pl.info["pn"], ws2)
+    out = pdm.reconstruct_device(pl, ws2)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)

@@ -267,6 +267,47 @@ def test_tuning_table_rejects_bad_entries(builtin_tuning, bad):
     assert pdm.get_tuning() == before  # no change
 
 
+def test_capped_plan_cuts_one_prime_into_grid_slabs():
+    # below one prime's footprint the plan cuts each prime's grid into slabs along the second
+    # variable: the least power of two that fits, at most half that variable's grid, and
+    # never below what the determinants and the coefficient residues need whole
+    H = pdm.HOST_ONLY
+    arr = W.config2()
+    one = None
+    for cap in range(40 << 20, 4 << 20, -(1 << 19)):
+        try:
+            info = pdm.plan(12, (3, 3, 3), host_coeffs=arr, flags=H, max_workspace=cap).info
+        except pdm.PolydetError as e:
+            assert e.status == B.EUNSUPPORTED
+            floor = cap
+            break
+        assert info["workspace_bytes"] <= cap
+        if info["grid_slabs"] == 1:
+            one = info["workspace_bytes"]  # the smallest footprint without slabs
+            continue
+        assert info["prime_group"] == 1 and info["workspace_bytes"] < one
+        sl = info["grid_slabs"]
+        assert sl & (sl - 1) == 0 and 2 <= sl <= info["N"][1] // 2
+        assert info["det_left_looking"] == 0
+        last = info
+    assert one is not None and last["grid_slabs"] >= 8
+    # the whole grid's determinants (numerators and denominators) and every prime's
+    # coefficient residues stay in the workspace
+    assert floor >= 2 * 4 * last["G"] + last["coef_bytes"]
+    # slabs need a second variable
+    one_var = W.random_matrix(np.random.default_rng(3), 6, (7,), -9, 9)
+    info = pdm.plan(6, (7,), host_coeffs=one_var, flags=H).info
+    with pytest.raises(pdm.PolydetError) as e:
+        pdm.plan(6, (7,), host_coeffs=one_var, flags=H,
+                 max_workspace=info["workspace_bytes"] // 2)
+    assert e.value.status == B.EUNSUPPORTED
+    # stage timing needs the whole grid at once
+    with pytest.raises(pdm.PolydetError) as e:
+        pdm.plan(12, (3, 3, 3), host_coeffs=arr, flags=H | pdm.STAGE_TIMING,
+                 max_workspace=last["workspace_bytes"])
+    assert e.value.status == B.EINVAL
+
+
 def test_capped_workspace_groups_primes():
     H = pdm.HOST_ONLY
     arr = W.config2()
@@ -333,6 +374,24 @@ def test_bench_algorithmic_figures():
     assert bench.det_updates(12) == 506
     assert bench.expand_bytes(7, 101, [4, 4, 4], [64, 64, 64]) == 4 * 7 * 101 * (64 + 2 * 1024 + 16384)
     assert bench.expand_bytes(3, 5, [2], [8]) == 0  # one variable: evaluated inside the elimination
+    # issue cost of the two-column elimination (CU-clocks per lane): (m-2)^2 updates of
+    # 5 multiply-class + 1 plain op and m-2 column-factor pairs of 8 + 7, then a 2x2 for even n
+    upd, col, two = 5 / 64 + 1 / 128, 8 / 64 + 7 / 128, 4 / 64 + 2 / 128
+    assert bench.det_issue_clk(1) == 0
+    assert bench.det_issue_clk(2) == pytest.approx(two)
+    assert bench.det_issue_clk(3) == pytest.approx(upd + col)
+    assert bench.det_issue_clk(4) == pytest.approx(4 * upd + 2 * col + two)
+    assert bench.det_issue_clk(5) == pytest.approx(9 * upd + 3 * col + upd + col)
+    # first-variable evaluation per entry and point: paired (2..4 coefficients) one two-product
+    # reduction and an addition; otherwise ceil(m0/2) reductions and the additions between them
+    assert bench.eval_issue_clk(1) == 0
+    assert bench.eval_issue_clk(4) == pytest.approx(two + 1 / 128)
+    assert bench.eval_issue_clk(6) == pytest.approx(3 * two + 2 * 3 / 128)
+    # the peak of a launch counts both; elimination alone is faster
+    mix = [(12, 1000, 101, 4)]
+    assert bench.alu_peak_updates(mix) < bench.alu_peak_updates_elimination_only(mix)
+    assert bench.alu_peak_updates_elimination_only(mix) == pytest.approx(
+        506 / bench.det_issue_clk(12) * 256 * 2.4e9)
 
 
 def test_plan_with_coefficients_is_specialised_to_their_zero_pattern():
