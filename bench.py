@@ -107,7 +107,7 @@ def nonzero_entries(a) -> int:
 # FETCH_SIZE (22,850 KiB) and WRITE_SIZE (14,336 KiB) passes, scaled by what the same counters
 # read for a 1 GiB device copy (FETCH x 2.0, WRITE x 1.0), valid only for the kernel sources and
 # tuning table they were taken with (their hash).
-DET_TRAFFIC = {"sources_sha256_16": "388e0bde3ee0a621", "bytes": 46.80e6 + 14.68e6}
+DET_TRAFFIC = {"sources_sha256_16": "54a4f109cdecc073", "bytes": 46.80e6 + 14.68e6}
 
 STAGES = ("reduce", "evaluate", "determinants", "finalize", "interpolate", "reconstruct")
 
@@ -266,15 +266,29 @@ def timed_each(fn, steps, stream):
     return ev[0].elapsed_time(ev[steps]), per
 
 
+def timed_total(fn, reps, stream):
+    """ms of `reps` calls of fn() between one pair of events on `stream` (no event between the
+    calls: each event costs a few microseconds of device time)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
 def stage_kernel_ms(pl, d_coeffs, out, ws, reps, stream):
     """Mean device ms of each stage's kernels, each stage run `reps` times back to back on a
     finished workspace (polydet_solve_stages) between two events: kernel durations without
-    any event between the kernels of a stage."""
+    any event between the kernels of a stage or between the repetitions."""
     import paper_2010_12117_amd as pdm
     res = {}
     for s, name in enumerate(STAGES):
-        total, _ = timed_each(lambda: pdm.solve_stages_device(pl, s, s + 1, d_coeffs, out, ws,
-                                                              stream=stream), reps, stream)
+        total = timed_total(lambda: pdm.solve_stages_device(pl, s, s + 1, d_coeffs, out, ws,
+                                                            stream=stream), reps, stream)
         res[name] = total / reps
     return res
 
@@ -301,7 +315,8 @@ def config2_roofline(reps=50):
     stream = torch.cuda.current_stream()
     for _ in range(20):
         pdm.solve_device(pl, d, out, ws)
-    total, per = timed_each(lambda: pdm.solve_device(pl, d, out, ws), reps, stream)
+    total = timed_total(lambda: pdm.solve_device(pl, d, out, ws), reps, stream)
+    _, per = timed_each(lambda: pdm.solve_device(pl, d, out, ws), reps, stream)
     stage = stage_kernel_ms(pl, d, out, ws, reps, stream)
     nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
     work = pn * G * det_updates(n)
@@ -547,8 +562,11 @@ def bench_single(args):
         del src, dst
     for _ in range(args.warmup):
         pdm.solve_device(pl, d, out, ws)
-    total, per = timed_each(lambda: pdm.solve_device(pl, d, out, ws), args.steps, stream)
+    # the timed region: K solves between one pair of events; then K more with an event after
+    # each for the median
+    total = timed_total(lambda: pdm.solve_device(pl, d, out, ws), args.steps, stream)
     ms = total / args.steps
+    _, per = timed_each(lambda: pdm.solve_device(pl, d, out, ws), args.steps, stream)
     stage = stage_kernel_ms(pl, d, out, ws, args.steps, stream)
     nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
     work = pn * G * det_updates(n)

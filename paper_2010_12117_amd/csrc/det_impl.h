@@ -253,16 +253,19 @@ __device__ __forceinline__ DetFrac eliminate(uint32_t (&a)[(N + GL - 1) / GL][N]
   return f;
 }
 
-// Waves per SIMD asked of the compiler for the single-matrix elimination kernels where it
-// lands just above an occupancy step by itself. With one lane per matrix (paired kernel) the
-// request is the lane's n^2 values plus kDetRegMargin, out of 512 registers per lane: 168 at
-// n = 12 (169 unasked: two waves) without spills. At n = 32 with 8 lanes (171-175 unasked)
-// three waves cost a few spilled values and were measured 7-8% faster; at n = 31 they were
-// not. Every other kernel gets no request (1: the launch bounds alone).
+// Waves per SIMD asked of the compiler for the elimination kernels (single-matrix and batched)
+// where it lands just above an occupancy step by itself. With one lane per matrix (paired
+// kernel) the request is the lane's n^2 values plus kDetRegMargin, out of 512 registers per
+// lane: 168 at n = 12 (169 unasked: two waves) without spills. At n = 32 with 8 lanes (171-175
+// unasked) three waves cost a few spilled values and were measured 7-8% faster; at n = 31 they
+// were not. Every other kernel gets no request (1: the launch bounds alone).
 constexpr int kDetRegMargin = 24;
 template <int N, int GL, bool PAIR>
 constexpr int det_waves() {
   if (GL == 8 && N == 32) return 3;
+  // 4 lanes from order 21: the kernels land at 164-187 VGPRs (2 waves); asked for 3 they spill
+  // up to 14 values and ran the 4096-matrix batch 5% faster, batched and plain alike
+  if (GL == 4 && N >= 21) return 3;
   if (GL != 1 || !PAIR) return 1;
   constexpr int regs = ((N * N + kDetRegMargin + 7) / 8) * 8;
   constexpr int w = 512 / regs;
@@ -524,12 +527,14 @@ __device__ __forceinline__ void det_fused_body(
 
 // The hardware hands a launch's workgroups to the 8 XCDs of the chip in turn (linear id mod
 // 8), and each XCD has its own L2. Neighbouring tiles read neighbouring 32-byte pieces of the
-// same 128-byte lines of the pre-tensor, so tile t is given to the workgroup that makes
-// consecutive tiles run on one XCD: with x blocks per row of the grid (a multiple of 8),
-// block b takes tile (b mod 8) x/8 + b / 8. Other grids keep the identity.
+// same 128-byte lines of the pre-tensor, so within every 32 consecutive workgroups the 4 that
+// an XCD receives take 4 consecutive tiles: block 32 g + 8 q + x takes tile 32 g + 4 x + q.
+// The order over the whole launch stays interleaved, which keeps the XCDs evenly loaded when
+// tiles differ in cost (a batch puts its largest grids first). The last nb mod 32 blocks (in
+// a grid row of nb) keep the identity.
 __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
-  if (nb % 8 != 0) return b;
-  return (b % 8) * (nb / 8) + b / 8;
+  if (b >= (nb & ~(int64_t)31)) return b;
+  return (b & ~(int64_t)31) | ((b & 7) << 2) | ((b >> 3) & 3);
 }
 
 template <int N, int GL>
@@ -582,7 +587,8 @@ __device__ __forceinline__ void det_fused_batch_body(uint32_t* tile, const BDet*
 }
 
 template <int N, int GL>
-__global__ __launch_bounds__(kDetBlock) void det_fused_batch_kernel(
+__global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_waves<N, GL, false>())))
+void det_fused_batch_kernel(
     const BDet* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws,
     bool fixup) {
   extern __shared__ uint32_t tile[];
@@ -590,7 +596,8 @@ __global__ __launch_bounds__(kDetBlock) void det_fused_batch_kernel(
 }
 
 template <int N, int GL>
-__global__ __launch_bounds__(kDetBlock) void det_fused_pair_batch_kernel(
+__global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_waves<N, GL, true>())))
+void det_fused_pair_batch_kernel(
     const BDet* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws,
     bool fixup) {
   extern __shared__ uint32_t tile[];
