@@ -48,16 +48,11 @@ struct BDet {
   const int32_t* slot;
 };
 
-struct BFinal {
-  int64_t block0;
-  int64_t detv_off, den_off, G;
-  int32_t pn, pad;
-  const PrimeConst* pc;
-};
-
 struct BIntt {
   int64_t block0;
   int64_t in_off, out_off, outer, inner, tw_stride, tiles;
+  int64_t den_off;  // the first pass: the denominators, divided into the numerators as they load
+                    // (-1 for the later passes)
   int32_t pn, Nv, logN, Dv1, W, pad;
   const uint32_t* itw;
   const PrimeConst* pc;
@@ -73,7 +68,7 @@ struct BGarner {
 
 // One launch of a batched solve.
 struct BLaunch {
-  enum Kind { kReduce, kExpand, kDet, kFinal, kIntt, kGarner } kind;
+  enum Kind { kReduce, kExpand, kDet, kIntt, kGarner } kind;
   size_t desc_off;     // byte offset of its descriptors in the plan's descriptor buffer
   int32_t ndesc;
   int64_t vblocks;     // virtual blocks in total
@@ -90,8 +85,6 @@ hipError_t batch_reduce(const BReduce* desc, int ndesc, int64_t vblocks, const i
                         const int64_t* coeff_offsets, uint8_t* ws, hipStream_t st);
 hipError_t batch_expand(const BExpand* desc, int ndesc, int64_t vblocks, uint8_t* ws,
                         hipStream_t st);
-hipError_t batch_final(const BFinal* desc, int ndesc, int64_t vblocks, uint8_t* ws,
-                       hipStream_t st);
 hipError_t batch_intt(const BIntt* desc, int ndesc, int64_t vblocks, size_t lds, uint8_t* ws,
                       hipStream_t st);
 hipError_t batch_garner(const BGarner* desc, int ndesc, int64_t vblocks, int pnmax, uint8_t* ws,

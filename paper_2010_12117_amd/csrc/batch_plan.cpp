@@ -234,30 +234,10 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
       }
       B.launches.push_back(L);
     }
-    // S3 end: det = num / den for every matrix of the chunk, one launch
-    {
-      std::vector<BFinal> d;
-      int64_t vb = 0;
-      for (size_t c = 0; c < chunk.size(); ++c) {
-        const MatPlan& P = mats[chunk[c]];
-        BFinal f{};
-        f.block0 = vb;
-        f.detv_off = (int64_t)reg[c].detv;
-        f.den_off = (int64_t)reg[c].den;
-        f.G = P.G;
-        f.pn = P.pn;
-        f.pc = P.d_pc;
-        d.push_back(f);
-        vb += (finalize_threads(P.G, P.pn) + 255) / 256;
-      }
-      BLaunch L{};
-      L.kind = BLaunch::kFinal;
-      L.desc_off = push(d.data(), d.size() * sizeof(BFinal));
-      L.ndesc = (int)d.size();
-      L.vblocks = vb;
-      B.launches.push_back(L);
-    }
-    // S4 interpolation passes: pass v covers the matrices with more than v variables
+    // S4 interpolation passes: pass v covers the matrices with more than v variables. The
+    // first pass also divides each point's numerator by its denominator as it loads (S3's
+    // end; every batched matrix has a variable), with enough lines per tile that a thread
+    // inverts kFuseBatch denominators with one exponentiation.
     for (int v = 0; v < maxk; ++v) {
       std::vector<BIntt> d;
       int64_t vb = 0;
@@ -274,7 +254,9 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         int logN = 0;
         while ((1 << logN) < Nv) ++logN;
         const int64_t lines = outer * inner;
-        const int W = intt_lines_per_block(lines, Nv, P.pn);
+        int W = intt_lines_per_block(lines, Nv, P.pn);
+        if (v == 0)
+          while (Nv * W < kFuseBatch * 256 && Nv * (2 * W) <= kTileElems) W <<= 1;
         BIntt e{};
         e.block0 = vb;
         e.in_off = (int64_t)in_off;
@@ -283,6 +265,7 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
         e.inner = inner;
         e.tw_stride = P.tw_stride;
         e.tiles = (lines + W - 1) / W;
+        e.den_off = v == 0 ? (int64_t)reg[c].den : -1;
         e.pn = P.pn;
         e.Nv = Nv;
         e.logN = logN;

@@ -108,7 +108,7 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
 // form): num = sign * (the last entry, or the last 2 x 2 determinant), 0 when the matrix is
 // singular; den = prod_s D_s^(m_s - 3) (the representative of 1 for a singular matrix, so
 // that den is never 0). The division is left to a later pass (the first interpolation pass,
-// or finalize_kernel for integer matrices and batches), which inverts the denominators of
+// or finalize_kernel for integer matrices), which inverts the denominators of
 // several points with one exponentiation. Every lane of the group returns the pair; all lanes
 // of the wave must call this together (lane broadcasts).
 // Entries may come in unreduced, in [0, 2p), and stay so: each step reduces only its two

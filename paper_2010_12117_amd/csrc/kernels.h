@@ -10,6 +10,8 @@ namespace pd {
 
 constexpr int kTileElems = 8192;  // interpolation tile: at most 32 KB of LDS per block (plus
                                   // the line's twiddles)
+constexpr int kFuseBatch = 8;     // denominators a thread of the first interpolation pass
+                                  // inverts together (one exponentiation)
 
 // Whether an elimination kernel is compiled for this order and lanes-per-matrix.
 bool det_config_supported(int n, int lanes);

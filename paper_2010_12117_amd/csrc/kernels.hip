@@ -102,7 +102,7 @@ __device__ __forceinline__ void expand_body(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t idx, int64_t B,
     int64_t outer, int m, int Nv, int JC, int64_t inner, int64_t nent,
     const uint32_t* __restrict__ tw, int64_t tw_stride, const PrimeConst* __restrict__ pcs,
-    const uint8_t* __restrict__ zero, bool write_zero, int jbase, int Nout) {
+    const uint8_t* __restrict__ zero, bool write_zero, int jbase, int Nout, int64_t idx_wave) {
   const bool paired = expand_paired(Nv, m);
   const int NJ = paired ? Nout / 2 : Nout;
   const int nJB = NJ / JC;
@@ -112,9 +112,7 @@ __device__ __forceinline__ void expand_body(
   const int64_t q = idx & (inner - 1);
   int64_t r;
   if constexpr (UJ) {
-    const int64_t idx0 = (int64_t)blockIdx.x * kBlock +
-                         64 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    r = idx0 >> li;
+    r = idx_wave >> li;  // the wave's first index (uniform across the wave)
   } else {
     r = idx >> li;
   }
@@ -185,20 +183,47 @@ __global__ __launch_bounds__(kBlock) void expand_kernel(
     int64_t tw_stride, const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
     bool write_zero, int jbase, int Nout) {
   const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t idx_wave =
+      (int64_t)blockIdx.x * kBlock + 64 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   // the single-matrix launches pick M = m up to 8 (launch_expand)
   expand_body<M, UJ, (M <= 8)>(in, out, idx, B, outer, m, Nv, JC, inner, nent, tw, tw_stride, pcs, zero,
-                     write_zero, jbase, Nout);
+                     write_zero, jbase, Nout, idx_wave);
+}
+
+// One virtual block of the batched pass, with the coefficient count M = d.m known at compile
+// time (the loop over the terms then has no runtime condition) and, for d.inner >= 64, the
+// wave-uniform form (UJ); both are uniform per virtual block.
+template <int M>
+__device__ __forceinline__ void expand_batch_vb(const BExpand& d, int64_t local, uint8_t* ws) {
+  const int64_t idx = local * kBlock + threadIdx.x;
+  const int64_t idx_wave = local * kBlock + 64 * __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t* in = (const uint32_t*)(ws + d.in_off);
+  uint32_t* out = (uint32_t*)(ws + d.out_off);
+  if (d.inner >= 64)
+    expand_body<M, true, true>(in, out, idx, d.B, d.outer, d.m, d.Nv, d.JC, d.inner, d.nent, d.tw,
+                               d.tw_stride, d.pc, d.zero, false, 0, d.Nv, idx_wave);
+  else
+    expand_body<M, false, true>(in, out, idx, d.B, d.outer, d.m, d.Nv, d.JC, d.inner, d.nent,
+                                d.tw, d.tw_stride, d.pc, d.zero, false, 0, d.Nv, idx_wave);
 }
 
 __global__ __launch_bounds__(kBlock) void expand_batch_kernel(const BExpand* __restrict__ desc,
                                                               int ndesc, int64_t vblocks,
                                                               uint8_t* __restrict__ ws) {
+  static_assert(kBatchMaxM == 8, "the dispatch below covers 1..8 coefficients");
   for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
     const BExpand& d = desc[find_desc(desc, ndesc, vb)];
-    const int64_t idx = (vb - d.block0) * kBlock + threadIdx.x;
-    expand_body<kBatchMaxM, false, false>((const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), idx,
-                            d.B, d.outer, d.m, d.Nv, d.JC, d.inner, d.nent, d.tw, d.tw_stride,
-                            d.pc, d.zero, false, 0, d.Nv);
+    const int64_t local = vb - d.block0;
+    switch (d.m) {
+      case 1: expand_batch_vb<1>(d, local, ws); break;
+      case 2: expand_batch_vb<2>(d, local, ws); break;
+      case 3: expand_batch_vb<3>(d, local, ws); break;
+      case 4: expand_batch_vb<4>(d, local, ws); break;
+      case 5: expand_batch_vb<5>(d, local, ws); break;
+      case 6: expand_batch_vb<6>(d, local, ws); break;
+      case 7: expand_batch_vb<7>(d, local, ws); break;
+      default: expand_batch_vb<8>(d, local, ws); break;
+    }
   }
 }
 
@@ -248,19 +273,6 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(const uint32_t* detv,
     finalize_body(detv, denv, quot, t, G, pcs);
 }
 
-__global__ __launch_bounds__(kBlock) void finalize_batch_kernel(const BFinal* __restrict__ desc,
-                                                                int ndesc, int64_t vblocks,
-                                                                uint8_t* __restrict__ ws) {
-  for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
-    const BFinal& d = desc[find_desc(desc, ndesc, vb)];
-    const int64_t t = (vb - d.block0) * kBlock + threadIdx.x;
-    if (t < (int64_t)d.pn * ((d.G + kFinalPoints - 1) / kFinalPoints)) {
-      // in place: the batched interpolation reads the determinants from detv
-      finalize_body((uint32_t*)(ws + d.detv_off), (const uint32_t*)(ws + d.den_off),
-                    (uint32_t*)(ws + d.detv_off), t, d.G, d.pc);
-    }
-  }
-}
 
 // ------------------------------------------------------------------------------------
 // S4: interpolation along one variable (inverse DFT: opposite sign in the exponent; the
@@ -275,7 +287,6 @@ __global__ __launch_bounds__(kBlock) void finalize_batch_kernel(const BFinal* __
 // kFuseBatch points with one exponentiation (simultaneous inversion) and puts num / den in the
 // tile. The numerators and denominators are left as they are (every stage reads only earlier
 // stages' outputs, so a stage can be run again).
-constexpr int kFuseBatch = 8;
 
 __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __restrict__ in,
                                           uint32_t* __restrict__ out, int64_t block,
@@ -423,7 +434,8 @@ __global__ __launch_bounds__(kBlock) void intt_batch_kernel(const BIntt* __restr
   for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
     const BIntt& d = desc[find_desc(desc, ndesc, vb)];
     intt_body(tile, (const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), vb - d.block0,
-              d.outer, d.Nv, d.logN, d.inner, d.Dv1, d.W, d.itw, d.tw_stride, d.pc);
+              d.outer, d.Nv, d.logN, d.inner, d.Dv1, d.W, d.itw, d.tw_stride, d.pc,
+              d.den_off >= 0 ? (const uint32_t*)(ws + d.den_off) : nullptr);
     __syncthreads();  // the next virtual block reuses the tile
   }
 }
@@ -899,12 +911,6 @@ hipError_t batch_expand(const BExpand* desc, int ndesc, int64_t vblocks, uint8_t
   return hipGetLastError();
 }
 
-hipError_t batch_final(const BFinal* desc, int ndesc, int64_t vblocks, uint8_t* ws,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(finalize_batch_kernel, dim3(persistent_grid(vblocks)), dim3(kBlock), 0, st,
-                     desc, ndesc, vblocks, ws);
-  return hipGetLastError();
-}
 
 hipError_t batch_intt(const BIntt* desc, int ndesc, int64_t vblocks, size_t lds, uint8_t* ws,
                       hipStream_t st) {

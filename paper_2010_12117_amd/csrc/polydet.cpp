@@ -246,7 +246,6 @@ int stage_of(pd::BLaunch::Kind k) {
     case pd::BLaunch::kReduce: return 0;
     case pd::BLaunch::kExpand: return 1;
     case pd::BLaunch::kDet: return 2;
-    case pd::BLaunch::kFinal: return 3;
     case pd::BLaunch::kIntt: return 4;
     default: return 5;
   }
@@ -595,9 +594,6 @@ static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
       case pd::BLaunch::kDet:
         e = pd::batch_det(L.n, L.lanes, L.ll, L.pair != 0, (const pd::BDet*)desc, L.ndesc,
                           L.vblocks, L.lds, ws, st);
-        break;
-      case pd::BLaunch::kFinal:
-        e = pd::batch_final((const pd::BFinal*)desc, L.ndesc, L.vblocks, ws, st);
         break;
       case pd::BLaunch::kIntt:
         e = pd::batch_intt((const pd::BIntt*)desc, L.ndesc, L.vblocks, L.lds, ws, st);
