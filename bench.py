@@ -358,7 +358,7 @@ def bench_batch(args):
     pl = pdm.plan_batch(mats)
     plan_s = time.perf_counter() - t0
     plain = pdm.plan_batch(mats, flags=pdm.BATCH_PLAIN)
-    side = None if args.no_extras else plan_batch_streams(pdm, mats, 4)  # side by side, 4 streams
+    serial = None if args.no_extras else plan_batch_streams(pdm, mats, 1)  # one stream
     timing = pdm.plan_batch(mats, flags=pdm.STAGE_TIMING)
     progress(f"plans built ({plan_s:.1f} s for the batched one)")
     infos = pl.infos
@@ -372,8 +372,10 @@ def bench_batch(args):
     dev = torch.device("cuda:0")
     d_coeffs = torch.from_numpy(np.concatenate([a.reshape(-1) for a in mats])).to(dev)
     d_out = torch.empty(o, dtype=torch.int32, device=dev)
-    ws = torch.empty(max(infos[0]["workspace_bytes"], plain.infos[0]["workspace_bytes"],
-                         timing.infos[0]["workspace_bytes"]), dtype=torch.uint8, device=dev)
+    ws = torch.empty(max([infos[0]["workspace_bytes"], plain.infos[0]["workspace_bytes"],
+                          timing.infos[0]["workspace_bytes"]] +
+                         ([serial.infos[0]["workspace_bytes"]] if serial is not None else [])),
+                     dtype=torch.uint8, device=dev)
     moddets = sum(i["pn"] * i["G"] for i in infos)
     updates = sum(i["pn"] * i["G"] * det_updates(i["n"]) for i in infos)
     stream = torch.cuda.Stream()
@@ -403,12 +405,12 @@ def bench_batch(args):
         _, per_plain = timed_each(lambda: solve(plain), args.plain_steps, stream)
         assert torch.equal(d_out, ref), "plain path differs from the batched solve"
         progress(f"plain: {statistics.median(per_plain):.1f} ms per solve")
-        per_side = [float("nan")]
-        if side is not None:
-            solve(side)
-            _, per_side = timed_each(lambda: solve(side), max(1, args.eager_steps), stream)
-            assert torch.equal(d_out, ref), "batched solve on 4 streams differs"
-            progress(f"batched on 4 streams (eager): {statistics.median(per_side):.1f} ms")
+        per_serial = [float("nan")]
+        if serial is not None:
+            solve(serial)
+            _, per_serial = timed_each(lambda: solve(serial), max(1, args.eager_steps), stream)
+            assert torch.equal(d_out, ref), "batched solve on one stream differs"
+            progress(f"batched on one stream (eager): {statistics.median(per_serial):.1f} ms")
         solve(timing)
         timing.stage_times()
         solve(timing)
@@ -453,7 +455,7 @@ def bench_batch(args):
                      "avg_ms_source": "HIP events before and after each elimination launch of "
                                       "one batched solve (sum)"},
         "plan_seconds": plan_s,
-        "batched_4_streams_eager_ms_median": statistics.median(per_side),
+        "batched_one_stream_eager_ms_median": statistics.median(per_serial),
     }
     if not args.no_extras:
         progress("small-matrix subset")
@@ -469,7 +471,8 @@ def bench_batch(args):
 
 
 def plan_batch_streams(pdm, mats, streams):
-    """A batched plan whose elimination launches use `streams` streams (the library reads
+    """A batched plan on `streams` streams: 1 runs every launch on the caller's stream, 2
+    (the default) runs consecutive chunks side by side (the library reads
     POLYDET_BATCH_STREAMS when the plan is made)."""
     old = os.environ.get("POLYDET_BATCH_STREAMS")
     os.environ["POLYDET_BATCH_STREAMS"] = str(streams)
@@ -683,6 +686,36 @@ def bench_serving(args):
     print(json.dumps(line), flush=True)
 
 
+def cpu_single_core(args):
+    """The oracle (pointwise integer Bareiss + exact interpolation) in one process, on the
+    single-matrix workloads: the 4x4 bivariate matrix, the 12x12 trivariate one and the 22x22
+    Sylvester matrix, whole; one JSON line with the seconds of each and their modular
+    determinants per second in the GPU metric's unit."""
+    import workloads as W
+    from oracle import det as OD
+    from oracle import plan as PL
+    cores, model = host_cpu()
+    out = {}
+    for name, make in (("4x4 bivariate degree 2", W.config1),
+                       ("12x12 trivariate degree 3", W.config2),
+                       ("22x22 Sylvester, bivariate degree 4 entries", W.config3a)):
+        arr = make()
+        n = arr.shape[0]
+        deg = [x - 1 for x in arr.shape[2:]]
+        D = PL.det_degree_bound_from_shape(n, deg)
+        t0 = time.perf_counter()
+        OD.det_pointwise(arr, D)
+        t = time.perf_counter() - t0
+        import paper_2010_12117_amd as pdm
+        info = pdm.plan(n, deg, host_coeffs=arr, flags=pdm.HOST_ONLY).info
+        out[name] = {"seconds": t, "modular_dets_per_s_equivalent": info["pn"] * info["G"] / t,
+                     "pn": info["pn"], "G": info["G"]}
+        progress(f"oracle, one core: {name}: {t:.1f} s")
+    print(json.dumps({"metric": "oracle on one host core (exact determinant, whole matrix)",
+                      "cores_used": 1, "host_cores": cores, "cpu": model, "results": out}),
+          flush=True)
+
+
 def calibrate_alu(args):
     """Vector-ALU throughput probes (include/polydet_calibrate.h) and the elimination update's
     peak derived from the published rates, beside the measured update rate."""
@@ -760,6 +793,8 @@ def main():
                          "traffic for scaling hardware byte counters)")
     ap.add_argument("--calibrate-alu", action="store_true",
                     help="run the vector-ALU throughput probes instead of a workload")
+    ap.add_argument("--cpu-single-core", action="store_true",
+                    help="time the oracle in one process on the single-matrix workloads")
     ap.add_argument("--probe-blocks", type=int, default=8192)
     ap.add_argument("--probe-iters", type=int, default=4096)
     args = ap.parse_args()
@@ -769,6 +804,9 @@ def main():
         sys.exit(2)
     if args.calibrate_alu:
         calibrate_alu(args)
+        return
+    if args.cpu_single_core:
+        cpu_single_core(args)
         return
     single = args.workload == "config2"
     if args.steps is None:

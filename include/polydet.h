@@ -90,12 +90,14 @@ typedef struct polydet_shape {
 #define POLYDET_DET_EXCHANGE ((uint32_t)8u)
 /* The workspace budget of one chunk of a batched solve is 16 GiB, or the value of the
  * environment variable POLYDET_BATCH_BUDGET_MB (in MiB) read when the plan is made; a single
- * matrix larger than the budget forms a chunk of its own. Every launch runs on the caller's
- * stream, in order. With the environment variable POLYDET_BATCH_STREAMS = k (2..16, read when
- * the plan is made) a chunk's elimination launches (one per order class) run side by side on
- * the caller's stream and k - 1 streams of the plan's own (default priority; forked from and
- * joined back into the caller's stream by events, so a captured solve stays one graph). Plans
- * made with POLYDET_STAGE_TIMING keep every launch on the caller's stream. */
+ * matrix larger than the budget forms a chunk of its own. Consecutive chunks run side by
+ * side: each chunk takes half the budget and alternates between the two halves of the
+ * workspace, even chunks on the caller's stream and odd ones on a stream of the plan's own
+ * (default priority; forked from and joined back into the caller's stream by events, so a
+ * captured solve stays one graph), so that one chunk's memory-bound passes overlap the next
+ * chunk's elimination. With the environment variable POLYDET_BATCH_STREAMS = 1 (read when the
+ * plan is made) every launch runs on the caller's stream, in chunks of the whole budget.
+ * Plans made with POLYDET_STAGE_TIMING run every launch on the caller's stream. */
 /* Plan flags. POLYDET_FORCE_PN(x): use exactly x primes (x >= the number the bound needs,
  * else EINVAL). POLYDET_PRIME_OFFSET(x): skip the first x primes of the table (a disjoint
  * prime set; the result does not depend on it). */

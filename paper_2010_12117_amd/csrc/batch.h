@@ -76,6 +76,7 @@ struct BLaunch {
   int32_t ll;          // elimination launches: left-looking form (lanes = 1) or repair pass
   int32_t pair;        // elimination launches: paired first-variable evaluation
   int32_t pnmax;       // reconstruction launches: largest prime count
+  int32_t chunk;       // the chunk of matrices the launch belongs to
   size_t lds;          // dynamic LDS per block
 };
 

@@ -71,8 +71,11 @@ bool batchable(const MatPlan& P) {
 
 size_t batch_footprint(const MatPlan& P) { return regions_of(P, 0).bytes; }
 
-std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPlan* out) {
+std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, bool halves,
+                        BatchPlan* out) {
   BatchPlan B;
+  B.halves = halves;
+  if (halves) budget /= 2;  // two chunks in the workspace at once
   // order: batchable matrices grouped by order n (fewer elimination launches per chunk),
   // largest grids first within an order; the rest are solved one by one
   std::vector<int> order;
@@ -106,10 +109,21 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
     return off;
   };
 
+  // with halves, chunk c lives in half c mod 2 of the workspace (each half as large as the
+  // largest chunk), so that consecutive chunks can run side by side
+  size_t half = 0;
   for (const auto& chunk : chunks) {
+    size_t sz = 0;
+    for (int i : chunk) sz = al256(sz + regions_of(mats[i], 0).bytes);
+    half = std::max(half, sz);
+  }
+  for (size_t ci = 0; ci < chunks.size(); ++ci) {
+    const auto& chunk = chunks[ci];
+    const size_t base0 = halves ? (ci % 2) * half : 0;
+    const size_t nb = B.launches.size();
     // layout
     std::vector<Regions> reg;
-    size_t base = 0;
+    size_t base = base0;
     for (int i : chunk) {
       reg.push_back(regions_of(mats[i], base));
       base = al256(base + reg.back().bytes);
@@ -317,6 +331,7 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPl
       L.pnmax = pnmax;
       B.launches.push_back(L);
     }
+    for (size_t li = nb; li < B.launches.size(); ++li) B.launches[li].chunk = (int32_t)ci;
   }
   B.desc_blob = std::move(blob);
   B.chunks = (int)chunks.size();

@@ -15,6 +15,7 @@ struct BatchPlan {
   std::vector<uint8_t> desc_blob;  // every launch's descriptors (uploaded once)
   std::vector<int> singles;        // matrices solved one by one after the chunks
   int chunks = 0;
+  bool halves = false;             // chunk c in half c mod 2 of the workspace
   size_t ws_bytes = 0;             // workspace the solve needs
 };
 
@@ -26,7 +27,10 @@ bool batchable(const MatPlan& P);
 size_t batch_footprint(const MatPlan& P);
 
 // Plans the batched solve of `mats` (device tables already uploaded) with chunks of at most
-// `budget` workspace bytes. Returns an error message or "".
-std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, BatchPlan* out);
+// `budget` workspace bytes in all; with `halves`, chunks of half the budget that alternate
+// between the two halves of the workspace (consecutive chunks share no memory and can run
+// on two streams). Returns an error message or "".
+std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, bool halves,
+                        BatchPlan* out);
 
 }  // namespace pd

@@ -80,16 +80,17 @@ polydet_status check_shape(const polydet_shape* s, pd::ShapeIn* out) {
 }
 
 constexpr size_t kBatchBudget = size_t(16) << 30;  // default workspace per chunk of a batch
-// Streams for a chunk's elimination launches. Side by side on 4 streams the 4096-matrix
-// workload took 3.97 s per eager solve against 3.92 s on the caller's stream alone (the
-// launches fill the chip by themselves and then compete for it), so one is the default.
-constexpr int kBatchStreams = 1;
+// Streams of a batched solve: 2 runs consecutive chunks side by side (each in its own half
+// of the workspace, on the caller's stream and one of the plan's), so that a chunk's
+// memory-bound passes overlap the next chunk's elimination; 1 runs every launch on the
+// caller's stream, chunks of the whole budget.
+constexpr int kBatchStreams = 2;
 
 int batch_streams() {
   const char* v = std::getenv("POLYDET_BATCH_STREAMS");
   if (v && *v) {
     const int k = std::atoi(v);
-    if (k >= 1 && k <= 16) return k;
+    if (k == 1 || k == 2) return k;
   }
   return kBatchStreams;
 }
@@ -109,7 +110,8 @@ polydet_status make_batch(polydet_plan_s* h, uint32_t flags) {
   h->batch = B;
   B->plain = (flags & POLYDET_BATCH_PLAIN) != 0;
   if (B->plain) return POLYDET_OK;
-  std::string err = pd::build_batch(h->plan.mats, batch_budget(), &B->bp);
+  const int ns = batch_streams();
+  std::string err = pd::build_batch(h->plan.mats, batch_budget(), ns == 2, &B->bp);
   if (!err.empty()) return fail(POLYDET_EINVAL, err);
   h->plan.ws_bytes = B->bp.ws_bytes;
   hipError_t e = hipMalloc((void**)&B->d_desc, std::max<size_t>(B->bp.desc_blob.size(), 256));
@@ -129,20 +131,17 @@ polydet_status make_batch(polydet_plan_s* h, uint32_t flags) {
     }
     return POLYDET_OK;  // timed solves keep every launch on the caller's stream, in order
   }
-  const int ns = batch_streams();
-  if (ns > 1) {
+  if (B->bp.halves && B->bp.chunks > 1) {
     if ((e = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming)) != hipSuccess)
       return hip_fail(e, "hipEventCreateWithFlags");
-    for (int i = 1; i < ns; ++i) {
-      hipStream_t sst = nullptr;
-      hipEvent_t ev = nullptr;
-      if ((e = hipStreamCreateWithFlags(&sst, hipStreamNonBlocking)) != hipSuccess)
-        return hip_fail(e, "hipStreamCreateWithFlags");
-      B->side.push_back(sst);
-      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
-        return hip_fail(e, "hipEventCreateWithFlags");
-      B->join.push_back(ev);
-    }
+    hipStream_t sst = nullptr;
+    hipEvent_t ev = nullptr;
+    if ((e = hipStreamCreateWithFlags(&sst, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "hipStreamCreateWithFlags");
+    B->side.push_back(sst);
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreateWithFlags");
+    B->join.push_back(ev);
   }
   return POLYDET_OK;
 }
@@ -536,76 +535,47 @@ static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
     T->pending = true;
   }
   const size_t nl = B->bp.launches.size();
+  // chunks side by side: odd chunks on the plan's stream, forked from the caller's stream
+  // after the offsets are in place and joined back before the matrices solved one by one
+  const bool side = !B->side.empty() && !T;
+  if (side) {
+    hipError_t e = hipEventRecord(B->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(B->side[0], B->fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "batch fork");
+  }
   for (size_t li = 0; li < nl; ++li) {
     const pd::BLaunch& L = B->bp.launches[li];
     const void* desc = B->d_desc + L.desc_off;
     hipError_t e = hipSuccess;
-    if (L.kind == pd::BLaunch::kDet && !B->side.empty() && !T) {
-      // The chunk's elimination launches (one per order class) read the evaluated entries and
-      // write disjoint determinant regions: they run side by side on the caller's stream and
-      // the side streams (fork and join by events), so that waves of different orders share
-      // the CUs' registers and issue slots. Largest work first, each to the least loaded
-      // stream; a left-looking pass and its repair stay together, in order.
-      size_t lj = li;
-      while (lj < nl && B->bp.launches[lj].kind == pd::BLaunch::kDet) ++lj;
-      const size_t nstreams = B->side.size() + 1;
-      std::vector<double> load(nstreams, 0.0);
-      std::vector<char> used(nstreams, 0);
-      if ((e = hipEventRecord(B->fork, st)) != hipSuccess) return hip_fail(e, "batch fork");
-      for (size_t k = li; k < lj;) {
-        const pd::BLaunch& D = B->bp.launches[k];
-        const size_t kn = (D.ll == 1 && k + 1 < lj) ? k + 2 : k + 1;  // the pass and its repair
-        size_t sidx = 0;
-        for (size_t q = 1; q < nstreams; ++q)
-          if (load[q] < load[sidx]) sidx = q;
-        hipStream_t sst = sidx == 0 ? st : B->side[sidx - 1];
-        if (sidx > 0 && !used[sidx]) {
-          if ((e = hipStreamWaitEvent(sst, B->fork, 0)) != hipSuccess)
-            return hip_fail(e, "batch fork");
-        }
-        used[sidx] = 1;
-        for (size_t m = k; m < kn; ++m) {
-          const pd::BLaunch& Dm = B->bp.launches[m];
-          e = pd::batch_det(Dm.n, Dm.lanes, Dm.ll, Dm.pair != 0,
-                            (const pd::BDet*)(B->d_desc + Dm.desc_off), Dm.ndesc, Dm.vblocks,
-                            Dm.lds, ws, sst);
-          if (e != hipSuccess) return hip_fail(e, "batched launch");
-        }
-        load[sidx] += (double)D.vblocks * (double)D.n * D.n * D.n / D.lanes;
-        k = kn;
-      }
-      for (size_t q = 1; q < nstreams; ++q) {
-        if (!used[q]) continue;
-        if ((e = hipEventRecord(B->join[q - 1], B->side[q - 1])) != hipSuccess ||
-            (e = hipStreamWaitEvent(st, B->join[q - 1], 0)) != hipSuccess)
-          return hip_fail(e, "batch join");
-      }
-      li = lj - 1;
-      continue;
-    }
-    if (T && (e = hipEventRecord(T->ev[2 * li], st)) != hipSuccess) return hip_fail(e, "stage timing");
+    const hipStream_t ls = side && (L.chunk % 2) ? B->side[0] : st;  // the launch's stream
+    if (T && (e = hipEventRecord(T->ev[2 * li], ls)) != hipSuccess) return hip_fail(e, "stage timing");
     switch (L.kind) {
       case pd::BLaunch::kReduce:
-        e = pd::batch_reduce((const pd::BReduce*)desc, L.ndesc, L.vblocks, d_coeffs, d_coff, ws, st);
+        e = pd::batch_reduce((const pd::BReduce*)desc, L.ndesc, L.vblocks, d_coeffs, d_coff, ws, ls);
         break;
       case pd::BLaunch::kExpand:
-        e = pd::batch_expand((const pd::BExpand*)desc, L.ndesc, L.vblocks, ws, st);
+        e = pd::batch_expand((const pd::BExpand*)desc, L.ndesc, L.vblocks, ws, ls);
         break;
       case pd::BLaunch::kDet:
         e = pd::batch_det(L.n, L.lanes, L.ll, L.pair != 0, (const pd::BDet*)desc, L.ndesc,
-                          L.vblocks, L.lds, ws, st);
+                          L.vblocks, L.lds, ws, ls);
         break;
       case pd::BLaunch::kIntt:
-        e = pd::batch_intt((const pd::BIntt*)desc, L.ndesc, L.vblocks, L.lds, ws, st);
+        e = pd::batch_intt((const pd::BIntt*)desc, L.ndesc, L.vblocks, L.lds, ws, ls);
         break;
       case pd::BLaunch::kGarner:
         e = pd::batch_garner((const pd::BGarner*)desc, L.ndesc, L.vblocks, L.pnmax, ws, d_out,
-                             d_ooff, st);
+                             d_ooff, ls);
         break;
     }
     if (e != hipSuccess) return hip_fail(e, "batched launch");
-    if (T && (e = hipEventRecord(T->ev[2 * li + 1], st)) != hipSuccess)
+    if (T && (e = hipEventRecord(T->ev[2 * li + 1], ls)) != hipSuccess)
       return hip_fail(e, "stage timing");
+  }
+  if (side) {
+    hipError_t e = hipEventRecord(B->join[0], B->side[0]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, B->join[0], 0);
+    if (e != hipSuccess) return hip_fail(e, "batch join");
   }
   for (int i : B->bp.singles) {
     polydet_status r = run_one(plan->plan.mats[i], d_coeffs + coeff_offsets[i],
