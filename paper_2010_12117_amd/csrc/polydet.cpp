@@ -6,6 +6,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -47,6 +48,7 @@ struct BatchState {
   std::vector<hipStream_t> side;         // default-priority streams beside the caller's
   hipEvent_t fork = nullptr;             // recorded on the caller's stream before a fork
   std::vector<hipEvent_t> join;          // one per side stream, waited for at the join
+  std::mutex mu;                         // one host thread at a time enqueues a solve
 };
 
 struct polydet_plan_s {
@@ -510,6 +512,9 @@ static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
                            const int64_t* coeff_offsets, uint32_t* d_out,
                            const int64_t* out_offsets, uint8_t* ws, hipStream_t st) {
   BatchState* B = plan->batch;
+  // the offsets, the timer and the fork/join events are the plan's: solves issued from
+  // several host threads take turns
+  std::lock_guard<std::mutex> lk(B->mu);
   const size_t count = plan->plan.mats.size();
   // device copies of the offsets, refreshed on the stream only when they change
   bool same = B->h_offsets.size() == 2 * count;
