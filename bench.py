@@ -65,14 +65,17 @@ def det_issue_clk(n: int) -> float:
 def eval_issue_clk(m0: int) -> float:
     """Minimal issue cost in CU-clocks per lane of evaluating one entry at one point along the
     first variable (m0 coefficients), as the elimination kernel does before eliminating: with
-    2..4 coefficients the values at j and j + N/2 share the even and odd sums, so a point costs
-    one two-product reduction (3 mad + 1 mul_lo + a conditional subtraction) and one addition;
-    otherwise ceil(m0/2) such reductions and one modular addition (3 plain) between each."""
+    2..6 coefficients the values at j and j + N/2 share the even and odd sums, so a point costs
+    one reduction of two or three products (3 or 4 mad + 1 mul_lo + a conditional subtraction)
+    and one addition; otherwise ceil(m0/2) two-product reductions and one modular addition
+    (3 plain) between each."""
     if m0 <= 1:
         return 0.0
     mm2 = 4 * MULT_CLK + 2 * PLAIN_CLK
     if 2 <= m0 <= 4:
         return mm2 + PLAIN_CLK
+    if m0 <= 6:
+        return mm2 + MULT_CLK + PLAIN_CLK
     r = (m0 + 1) // 2
     return r * mm2 + (r - 1) * 3 * PLAIN_CLK
 
@@ -162,9 +165,10 @@ def host_cpu():
 def det_kernel_name(info, batched=False):
     n, lanes = info["n"], info["det_lanes"]
     m0 = info["deg"][0] + 1 if info["nvars"] else 1
-    paired = 2 <= m0 <= 4  # first-variable points j0, j0 + N0/2 built by two lanes
+    paired = 2 <= m0 <= 6  # first-variable points j0, j0 + N0/2 built by two lanes
+    terms = 2 if m0 <= 4 else 3  # even or odd terms summed by each of the two
     fused = ("det_fused_pair" if paired else "det_fused") + ("_batch" if batched else "") + \
-        f"_kernel<{n},{lanes}>"
+        (f"_kernel<{n},{lanes},{terms}>" if paired else f"_kernel<{n},{lanes}>")
     if info["det_left_looking"]:
         return f"det_ll_kernel<{n}> + repair {fused}"
     return fused

@@ -308,7 +308,8 @@ const char* polydet_last_error(void);
 /* Limits of this build: maximum n, nvars, N[v] and pn. Any pointer may be NULL. */
 /* Launch-mapping table for the elimination kernel, per class c and matrix order n (1..32;
  * index 0 is unused). Class 0: the first variable has 2 to 4 coefficients (its evaluation is
- * paired across the wave's halves); class 1: any other matrix with at least one variable.
+ * paired across the wave's halves, two terms per lane); class 1: any other matrix with at
+ * least one variable (5 or 6 coefficients are paired too, three terms per lane).
  * An entry of 0 keeps the built-in choice; flags given to polydet_plan override the table.
  *   lanes         lanes that share one matrix: 1, 2, 4, 8 or 16 (the pairs the build
  *                 compiles: 1 for n <= 12, 2 for 2..16, 4 for 4..24, 8 for n >= 8, 16 for

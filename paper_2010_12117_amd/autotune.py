@@ -1,7 +1,8 @@
 """Autotuner of the elimination kernel's launch mapping (polydet_tuning in include/polydet.h).
 
 For every matrix order n and class (first variable with 2..4 coefficients, whose evaluation is
-paired across the wave's halves, or any other), it times the candidate mappings on the GPU:
+paired across the wave's halves with two terms per lane, or any other; its probe has 5
+coefficients, paired with three terms per lane), it times the candidate mappings on the GPU:
 * lanes per matrix: every count the build compiles for n;
 * points per LDS tile (Q): 4, 8, 16;
 * elimination form: the exchanging kernel, and for n <= 16 the left-looking pass + repair.

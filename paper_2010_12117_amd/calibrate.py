@@ -1,7 +1,7 @@
 """Measures the rates of the running-time prediction (polydet_rates in include/polydet.h).
 
 For every matrix order n in 2..32 and class (a first variable with 2..4 coefficients, whose
-evaluation is paired, or any other), a probe matrix with at least `min_dets` modular
+evaluation is paired with two terms per lane, or any other), a probe matrix with at least `min_dets` modular
 determinants per solve is solved once; then each stage is run again `reps` times by itself on
 the finished workspace (polydet_solve_stages) between two HIP events, which gives the stage's
 kernel time without events between its kernels. The elimination's rate is the probe's
@@ -28,7 +28,8 @@ CLASSES = ("paired", "other")
 
 def probe_matrix(n: int, cls: str, min_dets: int, rng: np.random.Generator) -> np.ndarray:
     """Random n x n matrix of the class with at least min_dets modular dets per solve: a first
-    variable with 4 coefficients (paired) or 6 (other), a quarter of the entries zero."""
+    variable with 4 coefficients (class "paired") or 6 (class "other": paired with three
+    terms per lane), a quarter of the entries zero."""
     first = 3 if cls == "paired" else 5
     arr = None
     for deg in ((first, 1), (first, 2), (first, 1, 1), (first, 2, 1), (first, 2, 2),

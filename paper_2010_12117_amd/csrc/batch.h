@@ -74,7 +74,8 @@ struct BLaunch {
   int64_t vblocks;     // virtual blocks in total
   int32_t n, lanes;    // elimination launches: order and lanes per matrix
   int32_t ll;          // elimination launches: left-looking form (lanes = 1) or repair pass
-  int32_t pair;        // elimination launches: paired first-variable evaluation
+  int32_t pair;        // elimination launches: terms per lane of the paired first-variable
+                       // evaluation (fused_pair_terms), 0 when unpaired
   int32_t pnmax;       // reconstruction launches: largest prime count
   int32_t chunk;       // the chunk of matrices the launch belongs to
   size_t lds;          // dynamic LDS per block
@@ -91,13 +92,14 @@ hipError_t batch_intt(const BIntt* desc, int ndesc, int64_t vblocks, size_t lds,
 hipError_t batch_garner(const BGarner* desc, int ndesc, int64_t vblocks, int pnmax, uint8_t* ws,
                         uint32_t* out, const int64_t* out_offsets, hipStream_t st);
 // ll = 1: left-looking launch; ll = 2: repair launch of the exchanging kernel (fixup);
-// ll = 0: the exchanging kernel. pair: every matrix of the launch has fused_paired(m0).
-hipError_t batch_det(int n, int lanes, int ll, bool pair, const BDet* desc, int ndesc,
+// ll = 0: the exchanging kernel. pair: every matrix of the launch has fused_paired(m0) with
+// that many fused_pair_terms, or 0: none has.
+hipError_t batch_det(int n, int lanes, int ll, int pair, const BDet* desc, int ndesc,
                      int64_t vblocks, size_t lds, uint8_t* ws, hipStream_t st);
 
 template <int N, int GL>
 hipError_t det_fused_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
-                                  uint8_t* ws, bool pair, bool fixup, hipStream_t st);
+                                  uint8_t* ws, int pair, bool fixup, hipStream_t st);
 template <int N>
 hipError_t det_ll_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
                                uint8_t* ws, hipStream_t st);

@@ -198,11 +198,12 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, bool ha
       B.launches.push_back(L);
     }
     // S3 elimination with the first variable's evaluation: one launch per (order, lanes,
-    // elimination form, paired evaluation)
+    // elimination form, terms per lane of the paired evaluation or 0)
     std::map<std::tuple<int, int, int, int>, std::vector<size_t>> classes;
     for (size_t c = 0; c < chunk.size(); ++c) {
       const MatPlan& P = mats[chunk[c]];
-      classes[{-P.n, P.det_lanes, P.det_ll ? 1 : 0, fused_paired(P.m[0]) ? 1 : 0}].push_back(c);
+      classes[{-P.n, P.det_lanes, P.det_ll ? 1 : 0,
+               fused_paired(P.m[0]) ? fused_pair_terms(P.m[0]) : 0}].push_back(c);
     }
     for (auto& kv : classes) {
       std::vector<BDet> d;

@@ -375,13 +375,14 @@ __device__ __forceinline__ bool block_needs_fixup(const uint32_t* __restrict__ d
 // matrix at the point (j0, r0 + q) as sum_m x_m w0^{m j0} (the evaluation of Section 2 along
 // x1) and eliminates it with row exchanges. Point index = j0 R + r.
 //
-// PAIR (2 <= m0 <= 4, fused_paired): j0 runs over [0, N0/2) and lanes l and l + 32 of a wave
-// build the points j0 and j0 + N0/2 of the same (slot, r) together. The lower lane sums the
-// even terms E = x0 + x2 w0^{2 j0}, the upper one the odd terms O = x1 w0^{j0} + x3 w0^{3 j0}
-// (one reduction each), they exchange the sums, and since w0^{N0/2} = -1 the values are
-// E + O and E - O: half the products and LDS reads of the unpaired form.
+// PT > 0 (paired, 2 <= m0 <= 2 PT, fused_paired): j0 runs over [0, N0/2) and lanes l and
+// l + 32 of a wave build the points j0 and j0 + N0/2 of the same (slot, r) together. The
+// lower lane sums the even terms E = x0 + x2 w0^{2 j0} (+ x4 w0^{4 j0}), the upper one the odd
+// terms O = x1 w0^{j0} + x3 w0^{3 j0} (+ x5 w0^{5 j0}), PT products under one reduction each;
+// they exchange the sums, and since w0^{N0/2} = -1 the values are E + O and E - O: half the
+// products and LDS reads of the unpaired form, and one reduction instead of m0 / 2.
 // One block's share of the fused kernel: prime `prime`, tile `bx` = (j-range, r-range).
-template <int N, int GL, bool PAIR>
+template <int N, int GL, int PT>
 __device__ __forceinline__ void det_fused_body(
     uint32_t* tile, const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv,
     uint32_t* __restrict__ denv, int64_t R,
@@ -389,6 +390,8 @@ __device__ __forceinline__ void det_fused_body(
     const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero,
     const int32_t* __restrict__ entry_slot, int64_t nslot, int prime, int64_t bx, bool fixup,
     int64_t Rout, int64_t seg, int64_t off1, int64_t off2) {
+  constexpr bool PAIR = PT > 0;
+  static_assert(PT == 0 || PT == 2 || PT == 3, "two or three terms per lane when paired");
   constexpr int C = (N + GL - 1) / GL;
   constexpr int NE = N * N;
   constexpr int NCP = C * GL;  // tile columns per row, padded for the last lane slot
@@ -437,13 +440,16 @@ __device__ __forceinline__ void det_fused_body(
       // out of the loop (they would be spilled to VGPR lanes and read back one by one)
 #pragma unroll
       for (int w = 0; w < (NE + 63) / 64; ++w) asm volatile("" : "+s"(zm[w]));
-      // terms m = half and m = half + 2 of every entry, weight w0^{m j0} (0 past m0 - 1,
-      // where the row index is clamped to a valid row); w0^0 is the representative of 1
-      const int ma = half, mb = half + 2;
+      // terms m = half, half + 2 (and half + 4 when PT = 3) of every entry, weight
+      // w0^{m j0} (0 past m0 - 1, where the row index is clamped to a valid row); w0^0 is
+      // the representative of 1
+      const int ma = half, mb = half + 2, mc = half + 4;
       const uint32_t wa = ma < m0 ? w0[(ma * j0c) & (N0 - 1)] : 0u;
       const uint32_t wb = mb < m0 ? w0[(mb * j0c) & (N0 - 1)] : 0u;
+      const uint32_t wc = PT == 3 && mc < m0 ? w0[(mc * j0c) & (N0 - 1)] : 0u;
       const uint32_t* ra = tile + ((ma < m0 ? ma : m0 - 1) * Q + q) * NEP + t;
       const uint32_t* rb = tile + ((mb < m0 ? mb : m0 - 1) * Q + q) * NEP + t;
+      const uint32_t* rc = tile + ((mc < m0 ? mc : m0 - 1) * Q + q) * NEP + t;
       const uint32_t sm = half ? ~0u : 0u, sc = half ? p + 1u : 0u;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -454,7 +460,8 @@ __device__ __forceinline__ void det_fused_body(
           if (GL == 1 && ((zm[e >> 6] >> (e & 63)) & 1ull)) {
             a[c][i] = 0u;
           } else {
-            const uint32_t v = mm2(ra[off], wa, rb[off], wb, p, pinv);
+            const uint32_t v = PT == 3 ? mm3(ra[off], wa, rb[off], wb, rc[off], wc, p, pinv)
+                                       : mm2(ra[off], wa, rb[off], wb, p, pinv);
             // every lane now holds E (the lower lane's v) and O (the upper lane's v). Keep
             // E + O (lower lane) or E + (p - O) (upper lane), as E + (O ^ sm) + sc: with
             // sm = -1 and sc = p + 1, (O ^ sm) + sc = p - O. Both lie below 2p and are left
@@ -546,12 +553,12 @@ void det_fused_kernel(
     const int32_t* __restrict__ slot, int64_t nslot, bool fixup, int64_t Rout, int64_t seg,
     int64_t off1, int64_t off2) {
   extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
-  det_fused_body<N, GL, false>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
+  det_fused_body<N, GL, 0>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
                                slot, nslot, blockIdx.y, xcd_tile(blockIdx.x, gridDim.x), fixup,
                                Rout, seg, off1, off2);
 }
 
-template <int N, int GL>
+template <int N, int GL, int PT>
 __global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_waves<N, GL, true>())))
 void det_fused_pair_kernel(
     const uint32_t* __restrict__ pre, uint32_t* __restrict__ detv, uint32_t* __restrict__ denv,
@@ -560,14 +567,14 @@ void det_fused_pair_kernel(
     const int32_t* __restrict__ slot, int64_t nslot, bool fixup, int64_t Rout, int64_t seg,
     int64_t off1, int64_t off2) {
   extern __shared__ uint32_t tile[];  // [m0][Q][n*n | 1]
-  det_fused_body<N, GL, true>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
+  det_fused_body<N, GL, PT>(tile, pre, detv, denv, R, N0, m0, Q, S, tw0, tw_stride, pcs, zero,
                               slot, nslot, blockIdx.y, xcd_tile(blockIdx.x, gridDim.x), fixup,
                               Rout, seg, off1, off2);
 }
 
 // Batched form: blocks walk the virtual blocks of every matrix of this order in the launch;
 // virtual block vb of matrix d is (prime, tile) = divmod(vb - block0, rtiles * jtiles).
-template <int N, int GL, bool PAIR>
+template <int N, int GL, int PT>
 __device__ __forceinline__ void det_fused_batch_body(uint32_t* tile, const BDet* __restrict__ desc,
                                                      int ndesc, int64_t vblocks,
                                                      uint8_t* __restrict__ ws, bool fixup) {
@@ -579,7 +586,7 @@ __device__ __forceinline__ void det_fused_batch_body(uint32_t* tile, const BDet*
   const int64_t local = vb - d.block0;
   const int64_t per_prime = d.rtiles * d.jtiles;
   const int prime = (int)(local / per_prime);
-  det_fused_body<N, GL, PAIR>(tile, (const uint32_t*)(ws + d.pre_off),
+  det_fused_body<N, GL, PT>(tile, (const uint32_t*)(ws + d.pre_off),
                               (uint32_t*)(ws + d.detv_off), (uint32_t*)(ws + d.den_off), d.R,
                               d.N0, d.m0, d.Q, d.S, d.tw0, d.tw_stride, d.pc, d.zero, d.slot,
                               d.nslot, prime, local - (int64_t)prime * per_prime, fixup, d.R,
@@ -592,16 +599,16 @@ void det_fused_batch_kernel(
     const BDet* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws,
     bool fixup) {
   extern __shared__ uint32_t tile[];
-  det_fused_batch_body<N, GL, false>(tile, desc, ndesc, vblocks, ws, fixup);
+  det_fused_batch_body<N, GL, 0>(tile, desc, ndesc, vblocks, ws, fixup);
 }
 
-template <int N, int GL>
+template <int N, int GL, int PT>
 __global__ __launch_bounds__(kDetBlock) __attribute__((amdgpu_waves_per_eu(det_waves<N, GL, true>())))
 void det_fused_pair_batch_kernel(
     const BDet* __restrict__ desc, int ndesc, int64_t vblocks, uint8_t* __restrict__ ws,
     bool fixup) {
   extern __shared__ uint32_t tile[];
-  det_fused_batch_body<N, GL, true>(tile, desc, ndesc, vblocks, ws, fixup);
+  det_fused_batch_body<N, GL, PT>(tile, desc, ndesc, vblocks, ws, fixup);
 }
 
 // ------------------------------------------------------------------------------------
@@ -788,16 +795,21 @@ hipError_t det_launch(const uint32_t* eval, uint32_t* detv, uint32_t* denv, int6
 
 template <int N, int GL>
 hipError_t det_fused_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,
-                                  uint8_t* ws, bool pair, bool fixup, hipStream_t st) {
+                                  uint8_t* ws, int pair, bool fixup, hipStream_t st) {
   if (vblocks < 1) return hipSuccess;
   if (vblocks > kMaxGridBlocks) return hipErrorInvalidConfiguration;
   const dim3 g((unsigned)vblocks);
-  if (pair)
-    hipLaunchKernelGGL((det_fused_pair_batch_kernel<N, GL>), g, dim3(kDetBlock), lds, st, desc,
-                       ndesc, vblocks, ws, fixup);
-  else
+  if (pair == 2)
+    hipLaunchKernelGGL((det_fused_pair_batch_kernel<N, GL, 2>), g, dim3(kDetBlock), lds, st,
+                       desc, ndesc, vblocks, ws, fixup);
+  else if (pair == 3)
+    hipLaunchKernelGGL((det_fused_pair_batch_kernel<N, GL, 3>), g, dim3(kDetBlock), lds, st,
+                       desc, ndesc, vblocks, ws, fixup);
+  else if (pair == 0)
     hipLaunchKernelGGL((det_fused_batch_kernel<N, GL>), g, dim3(kDetBlock), lds, st, desc, ndesc,
                        vblocks, ws, fixup);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -829,8 +841,12 @@ hipError_t det_fused_launch(const FusedDetArgs& f, hipStream_t st) {
   const int64_t jtiles = (fused_jrange(f.N0, f.m0) + f.S - 1) / f.S;
   const size_t lds = fused_tile_words(N, GL, f.m0, f.Q) * sizeof(uint32_t);
   const dim3 g((unsigned)(rtiles * jtiles), (unsigned)f.pn);
-  if (fused_paired(f.m0))
-    hipLaunchKernelGGL((det_fused_pair_kernel<N, GL>), g, dim3(kDetBlock), lds, st, f.pre,
+  if (fused_paired(f.m0) && fused_pair_terms(f.m0) == 2)
+    hipLaunchKernelGGL((det_fused_pair_kernel<N, GL, 2>), g, dim3(kDetBlock), lds, st, f.pre,
+                       f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs,
+                       f.zero, f.slot, f.nslot, f.fixup, f.Rout, f.seg, f.off1, f.off2);
+  else if (fused_paired(f.m0))
+    hipLaunchKernelGGL((det_fused_pair_kernel<N, GL, 3>), g, dim3(kDetBlock), lds, st, f.pre,
                        f.detv, f.denv, f.R, f.N0, f.m0, f.Q, f.S, f.tw0, f.tw_stride, f.pcs,
                        f.zero, f.slot, f.nslot, f.fixup, f.Rout, f.seg, f.off1, f.off2);
   else

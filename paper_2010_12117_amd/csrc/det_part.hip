@@ -13,7 +13,7 @@ namespace pd {
                                         int, const PrimeConst*, hipStream_t);         \
   template hipError_t det_fused_launch<N, GL>(const FusedDetArgs&, hipStream_t);          \
   template hipError_t det_fused_batch_launch<N, GL>(const BDet*, int, int64_t, size_t,    \
-                                                    uint8_t*, bool, bool, hipStream_t);
+                                                    uint8_t*, int, bool, hipStream_t);
 #define PD_LL(N)                                                                       \
   template hipError_t det_ll_launch<N>(const FusedDetArgs&, hipStream_t);              \
   template hipError_t det_ll_batch_launch<N>(const BDet*, int, int64_t, size_t, uint8_t*, \

@@ -688,7 +688,7 @@ struct SingleDet {
 
 template <int N, int GL>
 struct BatchDet {
-  static hipError_t run(int ll, bool pair, const BDet* desc, int ndesc, int64_t vblocks,
+  static hipError_t run(int ll, int pair, const BDet* desc, int ndesc, int64_t vblocks,
                         size_t lds, uint8_t* ws, hipStream_t st) {
     if (ll == 1) {
       if constexpr (N <= kLLMaxN) return det_ll_batch_launch<N>(desc, ndesc, vblocks, lds, ws, st);
@@ -926,7 +926,7 @@ hipError_t batch_garner(const BGarner* desc, int ndesc, int64_t vblocks, int pnm
   return launch_garner_batch<32>(desc, ndesc, vblocks, ws, out, out_offsets, st);
 }
 
-hipError_t batch_det(int n, int lanes, int ll, bool pair, const BDet* desc, int ndesc,
+hipError_t batch_det(int n, int lanes, int ll, int pair, const BDet* desc, int ndesc,
                      int64_t vblocks, size_t lds, uint8_t* ws, hipStream_t st) {
   return det_dispatch<BatchDet>(n, lanes, ll, pair, desc, ndesc, vblocks, lds, ws, st);
 }

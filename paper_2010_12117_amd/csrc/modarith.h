@@ -49,6 +49,12 @@ PD_HD uint32_t mm2(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t p, u
   return redc((uint64_t)a * b + (uint64_t)c * d, p, pinv);
 }
 
+// (a b + c d + e f) / R with every operand below p: t < 3 p^2 < p R, one reduction.
+PD_HD uint32_t mm3(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t e, uint32_t f,
+                   uint32_t p, uint32_t pinv) {
+  return redc((uint64_t)a * b + (uint64_t)c * d + (uint64_t)e * f, p, pinv);
+}
+
 // (a b + c d) / R in [0, 2p) with a, c <= p and b, d < 2p (t < 4 p^2 < p R for p < 2^30).
 PD_HD uint32_t mm2_lazy(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t p,
                         uint32_t pinv) {

@@ -334,7 +334,7 @@ std::string build_matplan(const ShapeIn& s, const int64_t* host_coeffs, uint32_t
 
   // the measured launch-mapping table, where it has an entry for this order and class
   const Tuning tune = get_tuning();
-  const int tclass = (s.k >= 1 && fused_paired(P.m[0])) ? 0 : 1;
+  const int tclass = tune_class(s.k, P.m[0]);
   P.det_lanes = default_det_lanes(P.n);
   if (tune.lanes[tclass][P.n] > 0) P.det_lanes = tune.lanes[tclass][P.n];
   const int dl = (int)((flags >> 4) & 0xF);

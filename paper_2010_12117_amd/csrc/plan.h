@@ -21,13 +21,18 @@ constexpr int kMaxPrimes = 32;     // reconstruction kernel registers
 constexpr int kLLMaxN = 16;        // largest order with a left-looking elimination kernel
 constexpr int kLLMaxM = 8;         // its limit on coefficients in the first variable
 
-// Fused first-variable evaluation in pairs, for 2 <= m0 <= 4 coefficients in the first
+// Fused first-variable evaluation in pairs, for 2 <= m0 <= 6 coefficients in the first
 // variable (its grid N0 is then even): lanes l and l + 32 of a wave take the points j0 and
 // j0 + N0/2. Since w^{N0/2} = -1, f(w^{j0 + N0/2}) = E - O where f(w^{j0}) = E + O splits f
 // into its even and odd terms; the lower lane sums the even terms, the upper lane the odd
-// ones, and they exchange the sums. A block then covers the first variable's grid index j0
-// in [0, N0/2) only, with half as many matrices per j-row.
-PD_HD bool fused_paired(int m0) { return m0 >= 2 && m0 <= 4; }
+// ones (fused_pair_terms of them, under one reduction), and they exchange the sums. A block
+// then covers the first variable's grid index j0 in [0, N0/2) only, with half as many
+// matrices per j-row.
+PD_HD bool fused_paired(int m0) { return m0 >= 2 && m0 <= 6; }
+PD_HD int fused_pair_terms(int m0) { return m0 <= 4 ? 2 : 3; }
+// Class of the launch-mapping and rate tables (polydet_tuning, polydet_rates): 0 for a first
+// variable with 2..4 coefficients, 1 for every other plan.
+PD_HD int tune_class(int k, int m0) { return (k >= 1 && m0 >= 2 && m0 <= 4) ? 0 : 1; }
 PD_HD int fused_jrange(int N0, int m0) { return fused_paired(m0) ? N0 / 2 : N0; }
 // matrices (lane groups) in one j-row of a block of `block` lanes
 PD_HD int fused_slots(int block, int lanes, int m0) {

@@ -562,7 +562,7 @@ static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
         e = pd::batch_expand((const pd::BExpand*)desc, L.ndesc, L.vblocks, ws, ls);
         break;
       case pd::BLaunch::kDet:
-        e = pd::batch_det(L.n, L.lanes, L.ll, L.pair != 0, (const pd::BDet*)desc, L.ndesc,
+        e = pd::batch_det(L.n, L.lanes, L.ll, L.pair, (const pd::BDet*)desc, L.ndesc,
                           L.vblocks, L.lds, ws, ls);
         break;
       case pd::BLaunch::kIntt:

@@ -60,7 +60,7 @@ double predict_ms(const MatPlan& P, const Rates& r) {
   }
   t += eval_bytes / pick(r.eval_bytes_per_s, def.eval_bytes_per_s);
   // S3 elimination
-  const int cls = (P.k >= 1 && fused_paired(P.m[0])) ? 0 : 1;
+  const int cls = tune_class(P.k, P.m[0]);
   const double upd = (double)(P.n - 1) * P.n * (2.0 * P.n - 1) / 6.0;
   t += pn * (double)P.G * upd / pick(r.det_updates_per_s[cls][P.n], def.det_updates_per_s[cls][P.n]);
   launches += P.det_ll ? 2 : 1;

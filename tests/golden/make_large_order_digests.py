@@ -1,9 +1,9 @@
 """Write large_order_oracle_digests.json: the oracle's exact determinant of matrices of order
 25-32 whose first variable has 1 or 5-7 coefficients.
 
-These shapes take the elimination kernels that evaluate the first variable term by term (the
-paired evaluation covers 2-4 coefficients only) with 8 or 16 lanes per matrix, the kernels of
-the 32 x 32 trivariate degree-5 serving job. Coefficients are drawn like the serving jobs'
+These shapes take the elimination kernels with 8 or 16 lanes per matrix whose first-variable
+evaluation is paired with three terms per lane (5 or 6 coefficients, as in the 32 x 32
+trivariate degree-5 serving job) or term by term (1 or 7 coefficients). Coefficients are drawn like the serving jobs'
 (uniform in [-2^16, 2^16], dense), so the prime count reaches 20-25 and the reconstruction
 runs its widest form.
 

@@ -63,7 +63,7 @@ def test_large_job_shape_and_kernel(solved):
     info = pl.info
     assert info["N"] == (256, 256, 256) and info["D"] == (160, 160, 160)
     assert info["pn"] >= 25 and info["det_lanes"] in (8, 16)
-    # six coefficients in the first variable: the term-by-term evaluation, not the paired one
+    # six coefficients in the first variable: the paired evaluation with three terms per lane
     assert info["deg"][0] + 1 == 6
 
 

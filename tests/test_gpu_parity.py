@@ -121,6 +121,12 @@ def test_every_order_default_lanes(n):
 LANE_CASES = [(n, gl) for n in (2, 4, 7, 8, 12, 13, 16, 17, 22, 24, 25, 31, 32)
               for gl in supported_lanes(n)]
 
+# first variable of degree 4 or 5 (5 or 6 coefficients): the paired evaluation with three terms
+# per lane, at every lane mapping of these orders
+PAIR3_ORDERS = {3: 4, 8: 5, 12: 4, 13: 5, 16: 4, 17: 5, 24: 4, 25: 5, 32: 5}
+PAIR3_CASES = [(n, gl) for n in PAIR3_ORDERS for gl in supported_lanes(n)]
+_pair3_oracle = {}
+
 
 @pytest.mark.parametrize("n,lanes", LANE_CASES)
 def test_every_lane_mapping(n, lanes):
@@ -130,6 +136,18 @@ def test_every_lane_mapping(n, lanes):
     got, pl, _ = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2) | pdm.DET_EXCHANGE)
     assert pl.info["det_lanes"] == lanes
     assert box_to_dict(got) == box_to_dict(oracle_box(arr))
+
+
+@pytest.mark.parametrize("n,lanes", PAIR3_CASES)
+def test_three_term_pairing_every_lane_mapping(n, lanes):
+    rng = np.random.default_rng(2500 + n)
+    arr = W.random_matrix(rng, n, (PAIR3_ORDERS[n],), -9, 9, zero_prob=0.3)
+    log2 = {1: 0, 2: 1, 4: 2, 8: 3, 16: 4}[lanes]
+    got, pl, _ = gpu_solve(arr, flags=pdm.DET_LANES_LOG2(log2) | pdm.DET_EXCHANGE)
+    assert pl.info["det_lanes"] == lanes
+    if n not in _pair3_oracle:
+        _pair3_oracle[n] = box_to_dict(oracle_box(arr))
+    assert box_to_dict(got) == _pair3_oracle[n]
 
 
 def vanishing_pivots(rng, n, deg, kind):
@@ -276,8 +294,12 @@ def test_stages_against_oracle_steps():
             assert mont_to_plain(cf[q, ci], p) == info["det_sign"] * exact.get(e, 0) * G % p
 
 
+# first-variable coefficient counts: 2-4 (paired, two terms per lane), 5-6 (paired, three),
+# 1 and 7 (term by term)
 FUSE_CASES = [(3, (2, 1), 1), (12, (3, 3, 3), 1), (13, (1, 2), 2), (22, (2, 1), 4),
-              (17, (1, 1, 1), 8), (30, (1, 2), 16), (9, (4,), 1), (5, (2, 0, 1), 2)]
+              (17, (1, 1, 1), 8), (30, (1, 2), 16), (9, (4,), 1), (5, (2, 0, 1), 2),
+              (14, (5, 1), 2), (20, (4, 1), 4), (11, (5, 1, 1), 1), (19, (6,), 4),
+              (10, (0, 2), 1), (26, (4, 1), 8)]
 
 
 @pytest.mark.parametrize("n,deg,lanes", FUSE_CASES)
@@ -329,18 +351,18 @@ def _large_order_cases():
 
 
 @pytest.mark.parametrize("idx", range(7))
-def test_large_orders_term_by_term_evaluation(idx):
-    # orders 25-32 whose first variable has 1 or 5-7 coefficients: the elimination kernels
-    # that evaluate that variable term by term (not in pairs), with 8 and 16 lanes per matrix
-    # and the default mapping, against the oracle's exact determinant (stored digests written
-    # by tests/golden/make_large_order_digests.py from the pointwise oracle)
+def test_large_orders_against_oracle_digests(idx):
+    # orders 25-32 whose first variable has 5 or 6 coefficients (the paired evaluation with
+    # three terms per lane) or 1 or 7 (the term-by-term evaluation), with 8 and 16 lanes per
+    # matrix and the default mapping, against the oracle's exact determinant (stored digests
+    # written by tests/golden/make_large_order_digests.py from the pointwise oracle)
     import json
     LG = _large_order_cases()
     from make_config4_digests import digest
     n, deg, seed = LG.CASES[idx]
     want = json.load(open(LG.OUT))["digests"][LG.case_key(n, deg, seed)]
     arr = LG.case_matrix(n, deg, seed)
-    assert not (2 <= deg[0] + 1 <= 4)  # not the paired form
+    assert not (2 <= deg[0] + 1 <= 4)  # not the two-term paired form
     for flags in (pdm.DET_LANES_LOG2(3), pdm.DET_LANES_LOG2(4), 0):
         got, pl, _ = gpu_solve(arr, flags=flags | pdm.DET_EXCHANGE)
         assert pl.info["pn"] >= 15

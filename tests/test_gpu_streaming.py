@@ -143,7 +143,7 @@ def test_grid_slabs_match_one_shot(cap_mb):
 @pytest.mark.parametrize("deg", [(5, 3), (2, 4, 1, 2), (3, 5, 2)])
 def test_grid_slabs_other_shapes_against_oracle(deg):
     # two variables (the sliced pass reads the residues), four variables (two passes before
-    # it), and an unpaired first variable (6 coefficients); half the smallest one-prime
+    # it), and a first variable of 6 coefficients (three terms per lane); half the smallest one-prime
     # footprint forces the most slabs that fit
     import torch
     rng = np.random.default_rng(90 + len(deg))

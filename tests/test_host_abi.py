@@ -382,11 +382,13 @@ def test_bench_algorithmic_figures():
     assert bench.det_issue_clk(3) == pytest.approx(upd + col)
     assert bench.det_issue_clk(4) == pytest.approx(4 * upd + 2 * col + two)
     assert bench.det_issue_clk(5) == pytest.approx(9 * upd + 3 * col + upd + col)
-    # first-variable evaluation per entry and point: paired (2..4 coefficients) one two-product
-    # reduction and an addition; otherwise ceil(m0/2) reductions and the additions between them
+    # first-variable evaluation per entry and point: paired (2..6 coefficients) one reduction
+    # of two or three products and an addition; otherwise ceil(m0/2) two-product reductions
+    # and the additions between them
     assert bench.eval_issue_clk(1) == 0
     assert bench.eval_issue_clk(4) == pytest.approx(two + 1 / 128)
-    assert bench.eval_issue_clk(6) == pytest.approx(3 * two + 2 * 3 / 128)
+    assert bench.eval_issue_clk(6) == pytest.approx(two + 1 / 64 + 1 / 128)
+    assert bench.eval_issue_clk(8) == pytest.approx(4 * two + 3 * 3 / 128)
     # the peak of a launch counts both; elimination alone is faster
     mix = [(12, 1000, 101, 4)]
     assert bench.alu_peak_updates(mix) < bench.alu_peak_updates_elimination_only(mix)
