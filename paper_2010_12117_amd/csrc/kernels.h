@@ -23,6 +23,11 @@ int64_t finalize_threads(int64_t G, int pn);  // threads of the det = num / den 
 
 hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st);
 hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st);
+// S1 and S2 together: the first evaluation pass reduces the integer coefficients as it loads
+// them (and stores the residues as S1 does), one launch fewer (run_reduce then run_evaluate
+// where there is no evaluation pass).
+hipError_t run_reduce_evaluate(const MatPlan& P, const int64_t* coeffs, uint8_t* ws,
+                               hipStream_t st);
 hipError_t run_det(const MatPlan& P, uint8_t* ws, hipStream_t st);       // numerators, denominators
 // Grid slabs (MatPlan::slabs > 1, fused plans with two or more variables): the passes over
 // variables k-1 .. 2 once, then for each slab b the pass over variable 1 for its points and

@@ -36,6 +36,15 @@ inline unsigned persistent_grid(int64_t vblocks) {
 // The residues are laid out by slot: slot u holds input entry slot_src[u] (the entries in
 // elimination row order, or only the distinct nonzero ones).
 // ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t reduce_coeff(int64_t c, uint32_t p, uint32_t pinv,
+                                                 uint32_t r2, uint32_t r3) {
+  const bool neg = c < 0;
+  const uint64_t a = neg ? (uint64_t)(-(c + 1)) + 1u : (uint64_t)c;
+  const uint32_t hi = (uint32_t)(a >> 32), lo = (uint32_t)a;
+  const uint32_t r = addm(mm(hi, r3, p, pinv), mm(lo, r2, p, pinv), p);
+  return neg ? negm(r, p) : r;
+}
+
 __device__ __forceinline__ void reduce_body(const int64_t* __restrict__ in,
                                             uint32_t* __restrict__ out, int64_t i, int64_t count,
                                             int pn, int64_t T,
@@ -43,14 +52,9 @@ __device__ __forceinline__ void reduce_body(const int64_t* __restrict__ in,
                                             const PrimeConst* __restrict__ pcs) {
   const int64_t u = i / T;
   const int64_t c = in[(int64_t)slot_src[u] * T + (i - u * T)];
-  const bool neg = c < 0;
-  const uint64_t a = neg ? (uint64_t)(-(c + 1)) + 1u : (uint64_t)c;
-  const uint32_t hi = (uint32_t)(a >> 32), lo = (uint32_t)a;
   for (int q = 0; q < pn; ++q) {
     const PrimeConst P = pcs[q];
-    uint32_t r = addm(mm(hi, P.r3, P.p, P.pinv), mm(lo, P.r2, P.p, P.pinv), P.p);
-    if (neg) r = negm(r, P.p);
-    out[(int64_t)q * count + i] = r;
+    out[(int64_t)q * count + i] = reduce_coeff(c, P.p, P.pinv, P.r2, P.r3);
   }
 }
 
@@ -97,12 +101,20 @@ __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(
 // A slab of the grid (capped plans, one prime's pass over variable 1 in parts): the output
 // holds Nout < Nv values per line, the points jbase + j and, paired, jbase + j + Nv/2 for
 // j in [0, Nout/2), stored at j and j + Nout/2. jbase = 0 and Nout = Nv give the whole line.
-template <int M, bool UJ, bool EXACT>
+//
+// RED (the first pass, over the last variable: inner = 1): the line's coefficients are read
+// from the integer input and reduced as they load (S1 in the same launch): slot `entry` is
+// input entry slot_src[entry], whose T = outer * m coefficients start at slot_src[entry] * T.
+// The line's first thread also stores the residues where S1 puts them (`res`, laid out like
+// `in`), so that every later stage can be run again from them.
+template <int M, bool UJ, bool EXACT, bool RED = false>
 __device__ __forceinline__ void expand_body(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t idx, int64_t B,
     int64_t outer, int m, int Nv, int JC, int64_t inner, int64_t nent,
     const uint32_t* __restrict__ tw, int64_t tw_stride, const PrimeConst* __restrict__ pcs,
-    const uint8_t* __restrict__ zero, bool write_zero, int jbase, int Nout, int64_t idx_wave) {
+    const uint8_t* __restrict__ zero, bool write_zero, int jbase, int Nout, int64_t idx_wave,
+    const int64_t* __restrict__ coeffs = nullptr, const int32_t* __restrict__ slot_src = nullptr,
+    uint32_t* __restrict__ res = nullptr) {
   const bool paired = expand_paired(Nv, m);
   const int NJ = paired ? Nout / 2 : Nout;
   const int nJB = NJ / JC;
@@ -133,11 +145,23 @@ __device__ __forceinline__ void expand_body(
     return;
   }
   const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv;
-  const uint32_t* src = in + bo * m * inner + q;
   const uint32_t* w = tw + (int64_t)prime * tw_stride;
   uint32_t x[M];
+  if constexpr (RED) {
+    const uint32_t r2 = pcs[prime].r2, r3 = pcs[prime].r3;
+    const int64_t* src = coeffs + (int64_t)slot_src[entry] * outer * m + (bo - b * outer) * m;
 #pragma unroll
-  for (int e = 0; e < M; ++e) x[e] = e < m ? src[(int64_t)e * inner] : 0u;
+    for (int e = 0; e < M; ++e) x[e] = e < m ? reduce_coeff(src[e], p, pinv, r2, r3) : 0u;
+    if (jb == 0) {
+#pragma unroll
+      for (int e = 0; e < M; ++e)
+        if (e < m) res[bo * m + e] = x[e];
+    }
+  } else {
+    const uint32_t* src = in + bo * m * inner + q;
+#pragma unroll
+    for (int e = 0; e < M; ++e) x[e] = e < m ? src[(int64_t)e * inner] : 0u;
+  }
   const int mask = Nv - 1;
   if (paired) {
     // unrolled so that the twiddle loads of several points are in flight together
@@ -167,13 +191,28 @@ __device__ __forceinline__ void expand_body(
             O = addm(O, mm(x[e], w[(e * jg) & mask], p, pinv), p);
         }
       }
-      dst[(int64_t)j * inner] = addm(E, O, p);
-      dst[(int64_t)(j + NJ) * inner] = subm(E, O, p);
+      // streaming stores: each output is written once and read by the next launch (at the
+      // 12 x 12 trivariate workload the pre-tensor pass took 12.5 against 13.8 us)
+      __builtin_nontemporal_store(addm(E, O, p), &dst[(int64_t)j * inner]);
+      __builtin_nontemporal_store(subm(E, O, p), &dst[(int64_t)(j + NJ) * inner]);
     }
   } else {
     // m == 1: the line is its constant term at every point
     for (int j = j0; j < j0 + JC; ++j) dst[(int64_t)j * inner] = x[0];
   }
+}
+
+// The first pass with the reduction of the integer coefficients (RED in expand_body).
+template <int M>
+__global__ __launch_bounds__(kBlock) void expand_reduce_kernel(
+    const int64_t* __restrict__ coeffs, const int32_t* __restrict__ slot_src,
+    uint32_t* __restrict__ res, uint32_t* __restrict__ out, int64_t B, int64_t outer, int m,
+    int Nv, int JC, int64_t nent, const uint32_t* __restrict__ tw, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs, const uint8_t* __restrict__ zero, bool write_zero) {
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  expand_body<M, false, (M <= 8), true>(nullptr, out, idx, B, outer, m, Nv, JC, 1, nent, tw,
+                                        tw_stride, pcs, zero, write_zero, 0, Nv, idx, coeffs,
+                                        slot_src, res);
 }
 
 template <int M, bool UJ>
@@ -572,13 +611,22 @@ __global__ __launch_bounds__(kBlock) void garner_batch_kernel(
 // ------------------------------------------------------------------------------------
 template <int M>
 hipError_t launch_expand_m(const MatPlan& P, const uint32_t* in, uint32_t* out, int64_t outer,
-                           int v, int64_t inner, int jbase, int Nout, hipStream_t st) {
+                           int v, int64_t inner, int jbase, int Nout, hipStream_t st,
+                           const int64_t* coeffs) {
   const int64_t B = (int64_t)P.pn * P.nslot;
   if (B == 0) return hipSuccess;  // every entry is zero
   const int JC = expand_outputs_per_thread(Nout, inner, P.m[v]);
   const int64_t work = B * outer * (expand_jrange(Nout, P.m[v]) / JC) * inner;
   // the full evaluation tensor (last pass of the unfused path) is read without zero flags
   const bool write_zero = v == 0;
+  if (coeffs) {  // the first pass (inner = 1, the whole line): reduce as the line loads
+    if (inner != 1 || jbase != 0 || Nout != P.N[v]) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((expand_reduce_kernel<M>), dim3(blocks_for(work)), dim3(kBlock), 0, st,
+                       coeffs, P.d_slot_src, const_cast<uint32_t*>(in), out, B, outer, P.m[v],
+                       P.N[v], JC, P.nslot,
+                       P.d_tw + P.tw_off[v], P.tw_stride, P.d_pc, P.d_slot_zero, write_zero);
+    return hipGetLastError();
+  }
   if (inner >= 64)
     hipLaunchKernelGGL((expand_kernel<M, true>), dim3(blocks_for(work)), dim3(kBlock), 0, st, in,
                        out, B, outer, P.m[v], P.N[v], JC, inner, P.nslot, P.d_tw + P.tw_off[v],
@@ -590,23 +638,25 @@ hipError_t launch_expand_m(const MatPlan& P, const uint32_t* in, uint32_t* out, 
   return hipGetLastError();
 }
 
-// The pass over variable v; with jbase, Nout a slab of its grid (expand_body).
+// The pass over variable v; with jbase, Nout a slab of its grid (expand_body); with coeffs
+// the first pass, reading the integer coefficients instead of the residues.
 hipError_t launch_expand(const MatPlan& P, const uint32_t* in, uint32_t* out, int64_t outer,
-                         int v, int64_t inner, hipStream_t st, int jbase = 0, int Nout = 0) {
+                         int v, int64_t inner, hipStream_t st, int jbase = 0, int Nout = 0,
+                         const int64_t* coeffs = nullptr) {
   const int m = P.m[v];
   if (Nout == 0) Nout = P.N[v];
   switch (m) {
-    case 1: return launch_expand_m<1>(P, in, out, outer, v, inner, jbase, Nout, st);
-    case 2: return launch_expand_m<2>(P, in, out, outer, v, inner, jbase, Nout, st);
-    case 3: return launch_expand_m<3>(P, in, out, outer, v, inner, jbase, Nout, st);
-    case 4: return launch_expand_m<4>(P, in, out, outer, v, inner, jbase, Nout, st);
-    case 5: return launch_expand_m<5>(P, in, out, outer, v, inner, jbase, Nout, st);
-    case 6: return launch_expand_m<6>(P, in, out, outer, v, inner, jbase, Nout, st);
-    case 7: return launch_expand_m<7>(P, in, out, outer, v, inner, jbase, Nout, st);
-    case 8: return launch_expand_m<8>(P, in, out, outer, v, inner, jbase, Nout, st);
+    case 1: return launch_expand_m<1>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
+    case 2: return launch_expand_m<2>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
+    case 3: return launch_expand_m<3>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
+    case 4: return launch_expand_m<4>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
+    case 5: return launch_expand_m<5>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
+    case 6: return launch_expand_m<6>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
+    case 7: return launch_expand_m<7>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
+    case 8: return launch_expand_m<8>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
     default:
-      if (m <= 16) return launch_expand_m<16>(P, in, out, outer, v, inner, jbase, Nout, st);
-      return launch_expand_m<32>(P, in, out, outer, v, inner, jbase, Nout, st);
+      if (m <= 16) return launch_expand_m<16>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
+      return launch_expand_m<32>(P, in, out, outer, v, inner, jbase, Nout, st, coeffs);
   }
 }
 
@@ -792,9 +842,10 @@ hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipS
 
 // The evaluation passes over the variables v with vlo <= v <= vhi, from the last variable
 // down (passes alternate tmpA, tmpB); with slab >= 0 the pass over variable 1 makes that slab
-// only.
+// only. With coeffs the first pass (over the last variable, which must be in the range and
+// not sliced) reads the integer coefficients and reduces them itself (S1 in that launch).
 hipError_t run_evaluate_passes(const MatPlan& P, uint8_t* ws, int vlo, int vhi, int slab,
-                               hipStream_t st) {
+                               hipStream_t st, const int64_t* coeffs = nullptr) {
   const uint32_t* in = (const uint32_t*)(ws + P.off_res);
   uint32_t* bufs[2] = {(uint32_t*)(ws + P.off_tmpA), (uint32_t*)(ws + P.off_tmpB)};
   int which = 0;
@@ -808,7 +859,8 @@ hipError_t run_evaluate_passes(const MatPlan& P, uint8_t* ws, int vlo, int vhi, 
       const SlabMap sm = slab_map(P, v == 1 ? slab : -1);
       hipError_t err = v == 1 && slab >= 0
                            ? launch_expand(P, in, out, outer, v, inner, st, sm.jbase, sm.Nout)
-                           : launch_expand(P, in, out, outer, v, inner, st);
+                           : launch_expand(P, in, out, outer, v, inner, st, 0, 0,
+                                           v == P.k - 1 ? coeffs : nullptr);
       if (err != hipSuccess) return err;
     }
     in = out;
@@ -820,6 +872,18 @@ hipError_t run_evaluate_passes(const MatPlan& P, uint8_t* ws, int vlo, int vhi, 
 hipError_t run_evaluate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
   if (P.k == 0) return hipSuccess;  // the residues are the values at the single point
   return run_evaluate_passes(P, ws, 0, P.k - 1, -1, st);
+}
+
+hipError_t run_reduce_evaluate(const MatPlan& P, const int64_t* coeffs, uint8_t* ws,
+                               hipStream_t st) {
+  // the residues themselves are the input of the elimination (no evaluation pass) or of
+  // nothing (every entry zero): the reduction keeps its own launch
+  const bool passes = P.k >= (P.fused ? 2 : 1);
+  if (!passes || P.nslot * P.T == 0) {
+    hipError_t err = run_reduce(P, coeffs, ws, st);
+    return err != hipSuccess ? err : run_evaluate(P, ws, st);
+  }
+  return run_evaluate_passes(P, ws, 0, P.k - 1, -1, st, coeffs);
 }
 
 hipError_t run_evaluate_upper(const MatPlan& P, uint8_t* ws, hipStream_t st) {

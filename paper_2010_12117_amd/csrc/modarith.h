@@ -84,10 +84,12 @@ PD_HD uint32_t subm(uint32_t a, uint32_t b, uint32_t p) {
 
 PD_HD uint32_t negm(uint32_t a, uint32_t p) { return a ? p - a : 0u; }
 
-// x~^e in Montgomery form (left-to-right binary powering; e is uniform across a wave).
+// x~^e in Montgomery form (left-to-right binary powering from the top set bit of e, so a
+// 30-bit exponent costs 29 squarings; e is uniform across a wave).
 PD_HD uint32_t mpow(uint32_t x, uint32_t e, uint32_t one, uint32_t p, uint32_t pinv) {
-  uint32_t r = one;
-  for (int b = 31; b >= 0; --b) {
+  if (e == 0u) return one;
+  uint32_t r = x;
+  for (int b = 30 - __builtin_clz(e); b >= 0; --b) {
     r = mm(r, r, p, pinv);
     if ((e >> b) & 1u) r = mm(r, x, p, pinv);
   }

@@ -281,8 +281,8 @@ polydet_status run_primes(const pd::MatPlan& P, const int64_t* d_coeffs, int b, 
   const int g = P.prime_group > 0 ? P.prime_group : P.pn;
   for (int lo = b; lo < e; lo += g) {
     const pd::MatPlan R = pd::prime_range_plan(P, lo, std::min(e, lo + g));
-    if ((err = pd::run_reduce(R, d_coeffs, ws, st)) != hipSuccess) return hip_fail(err, "reduce");
     if (R.slabs > 1) {
+      if ((err = pd::run_reduce(R, d_coeffs, ws, st)) != hipSuccess) return hip_fail(err, "reduce");
       // one prime's grid in slabs along variable 1: the pre-tensor holds one slab at a time,
       // the determinants fill the whole grid
       if ((err = pd::run_evaluate_upper(R, ws, st)) != hipSuccess) return hip_fail(err, "evaluate");
@@ -293,7 +293,8 @@ polydet_status run_primes(const pd::MatPlan& P, const int64_t* d_coeffs, int b, 
           return hip_fail(err, "determinants");
       }
     } else {
-      if ((err = pd::run_evaluate(R, ws, st)) != hipSuccess) return hip_fail(err, "evaluate");
+      if ((err = pd::run_reduce_evaluate(R, d_coeffs, ws, st)) != hipSuccess)
+        return hip_fail(err, "reduce and evaluate");
       if ((err = pd::run_det(R, ws, st)) != hipSuccess) return hip_fail(err, "determinants");
     }
     if ((err = pd::run_finalize(R, ws, st)) != hipSuccess) return hip_fail(err, "finalize");
@@ -336,6 +337,13 @@ polydet_status run_stages(const pd::MatPlan& P, int b, int e, const int64_t* d_c
     }
   }
   for (int s = b; s < e; ++s) {
+    if (s == 0 && e >= 2 && !ev) {
+      // S1 and S2 in one go: the first evaluation pass reduces the coefficients itself
+      if ((err = pd::run_reduce_evaluate(P, d_coeffs, ws, st)) != hipSuccess)
+        return hip_fail(err, "reduce and evaluate");
+      s = 1;
+      continue;
+    }
     if ((err = run_stage(P, s, d_coeffs, d_out, ws, st)) != hipSuccess)
       return hip_fail(err, kStageNames[s]);
     if (ev && (err = hipEventRecord(ev[s + 1], st)) != hipSuccess)
