@@ -12,7 +12,9 @@ beside it. The line also carries the 12 x 12 trivariate single-matrix workload's
 roofline (`roofline_config2`).
 
 Prints one JSON line (the repository's benchmark contract). Other modes:
+  --workload config1   the single 4 x 4 bivariate matrix (16^2 grid, 1 prime; launch-bound)
   --workload config2   the single 12 x 12 trivariate matrix (64^3 grid, 7 primes)
+  --workload config3   the single 22 x 22 Sylvester matrix (128^2 grid, 15 primes)
   --workload config5   the serving load (Poisson arrivals, p50/p99 latency)
   --calibrate-alu      vector-ALU throughput probes (one JSON line)
 """
@@ -230,9 +232,9 @@ def cpu_baseline_batch(mats, infos, budget_s):
 
 
 def cpu_baseline_single(arr, D, pn, G):
-    """The oracle (pointwise integer Bareiss + exact interpolation) on the whole 12 x 12
-    trivariate matrix on all host cores, plus a single-core figure extrapolated from 2000 of
-    its node determinants."""
+    """The oracle (pointwise integer Bareiss + exact interpolation) on the whole matrix on all
+    host cores, plus a single-core figure extrapolated from (up to) 2000 of its node
+    determinants."""
     import numpy as np
     from oracle import det as OD
     cores, model = host_cpu()
@@ -248,9 +250,10 @@ def cpu_baseline_single(arr, D, pn, G):
     single = (time.perf_counter() - t1) * len(nodes) / len(sample)
     return {"value": pn * G / t, "unit": "modular dets/s (equivalent)", "cores": cores,
             "kind": "oracle",
-            "sample": (f"the whole 12x12 trivariate matrix once: {int(np.prod([d + 1 for d in D]))} "
-                       f"integer-node Bareiss determinants + exact interpolation in {t:.2f} s on "
-                       f"{cores} processes ({model}); value = pn*G / wall time"),
+            "sample": (f"the whole {arr.shape[0]}x{arr.shape[0]} matrix once: "
+                       f"{int(np.prod([d + 1 for d in D]))} integer-node Bareiss determinants + "
+                       f"exact interpolation in {t:.2f} s on {cores} processes ({model}); "
+                       "value = pn*G / wall time"),
             "exact_dets_per_s": 1.0 / t,
             "single_core_node_dets_s_extrapolated": single}
 
@@ -537,8 +540,44 @@ def bench_small_subset(mats, args, max_n=12):
             "value_batched": moddets / (res["batched"] / 1e3)}
 
 
+# The single-matrix workloads: generator name in workloads/ and description.
+SINGLE_WORKLOADS = {
+    "config1": ("config1", "4x4 bivariate degree-2 matrix, coefficients U[-10,10], dense, "
+                           "16^2 grid, 1 prime"),
+    "config2": ("config2", "12x12 trivariate degree-3 matrix, coefficients U[-1000,1000], 30% "
+                           "zero entries, 64^3 grid, 7 primes"),
+    "config3": ("config3a", "22x22 Sylvester matrix of two polynomials of degree 12 and 10 in x "
+                            "whose coefficients are dense bivariate degree-4 polynomials with "
+                            "coefficients U[-32768,32768], 128^2 grid, 15 primes"),
+}
+
+
+def graph_replay_ms(pl, d, out, ws, reps):
+    """ms per solve of `reps` replays of one solve captured in a HIP graph (no host launch
+    overhead), between one pair of events; the replays equal the eager solve."""
+    import torch
+
+    import paper_2010_12117_amd as pdm
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        pdm.solve_device(pl, d, out, ws, stream=stream)
+    stream.synchronize()
+    want = out.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        pdm.solve_device(pl, d, out, ws, stream=stream)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        g.replay()
+        total = timed_total(g.replay, reps, stream)
+    if not torch.equal(out, want):
+        raise RuntimeError("graph replay differs from the eager solve")
+    return total / reps
+
+
 def bench_single(args):
-    """The 12 x 12 trivariate matrix alone (64^3 grid, 7 primes)."""
+    """One matrix alone: the 4 x 4 bivariate (config1), 12 x 12 trivariate (config2) or 22 x 22
+    Sylvester (config3) workload."""
     import numpy as np
     import torch
 
@@ -546,8 +585,10 @@ def bench_single(args):
     import workloads as W
     from oracle import plan as PL
 
-    arr = W.config2()
-    n, deg = 12, (3, 3, 3)
+    gen, description = SINGLE_WORKLOADS[args.workload]
+    arr = getattr(W, gen)()
+    n = arr.shape[0]
+    deg = tuple(x - 1 for x in arr.shape[2:])
     flags = 0
     if args.det_lanes:
         flags |= pdm.DET_LANES_LOG2(args.det_lanes.bit_length() - 1)
@@ -574,6 +615,7 @@ def bench_single(args):
     total = timed_total(lambda: pdm.solve_device(pl, d, out, ws), args.steps, stream)
     ms = total / args.steps
     _, per = timed_each(lambda: pdm.solve_device(pl, d, out, ws), args.steps, stream)
+    graph_ms = graph_replay_ms(pl, d, out, ws, args.steps)
     stage = stage_kernel_ms(pl, d, out, ws, args.steps, stream)
     nnz = int(np.count_nonzero(np.abs(arr).reshape(n * n, -1).sum(axis=1)))
     work = pn * G * det_updates(n)
@@ -581,7 +623,8 @@ def bench_single(args):
     mix = [(n, pn * G, nnz, deg[0] + 1)]
     peak = alu_peak_updates(mix) / 1e12
     traffic = (DET_TRAFFIC["bytes"]
-               if kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
+               if args.workload == "config2"
+               and kernel_sources_hash() == DET_TRAFFIC["sources_sha256_16"] else None)
     eval_bytes = expand_bytes(pn, nnz, [x + 1 for x in deg], list(info["N"]))
     line = {
         "metric": "modular dets/sec (prime x point), exact poly det end to end, 1 GPU",
@@ -590,11 +633,11 @@ def bench_single(args):
         "ms_per_step_median": statistics.median(per), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32 (mod p < 2^30)",
         "data": "synthetic (seeded)",
-        "config": {"workload": "12x12 trivariate degree-3 matrix, coefficients U[-1000,1000], "
-                               "30% zero entries, 64^3 grid, 7 primes",
-                   "n": n, "nvars": 3, "deg": list(deg), "grid": list(info["N"]), "primes": pn,
-                   "nonzero_entries": nnz},
+        "config": {"workload": description,
+                   "n": n, "nvars": len(deg), "deg": list(deg), "grid": list(info["N"]),
+                   "primes": pn, "nonzero_entries": nnz},
         "exact_dets_per_s": 1e3 / ms,
+        "ms_per_step_graph": graph_ms,
         "stage_kernel_ms": stage,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "T elimination-updates/s", "frac": achieved / peak,
@@ -602,12 +645,13 @@ def bench_single(args):
                      "work_per_launch": work, "avg_ms": stage["determinants"],
                      "frac_elimination_only": achieved / (alu_peak_updates_elimination_only(mix) / 1e12),
                      "frac_of_single_step_peak": achieved / (SINGLE_STEP_PEAK_UPDATES / 1e12)},
-        "roofline_other": {"bound": "hbm", "achieved": eval_bytes / (stage["evaluate"] / 1e3) / 1e9,
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": eval_bytes / (stage["evaluate"] / 1e3) / 1e9 / HBM_PEAK_GBS,
-                           "traffic": None, "kernel": "expand_kernel (evaluation passes)",
-                           "bytes_per_solve": eval_bytes, "avg_ms": stage["evaluate"]},
     }
+    if eval_bytes and stage["evaluate"] > 0:
+        gbs = eval_bytes / (stage["evaluate"] / 1e3) / 1e9
+        line["roofline_other"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                                  "kernel": "expand_kernel (evaluation passes)",
+                                  "bytes_per_solve": eval_bytes, "avg_ms": stage["evaluate"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_single(arr, PL.det_degree_bound_from_shape(n, deg),
                                                    pn, G)
@@ -765,9 +809,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 5 batch solves; 200 single solves for config2)")
+                    help="timed steps (default: 5 batch solves; 200 for a single matrix)")
     ap.add_argument("--warmup", type=int, default=None,
-                    help="untimed steps first (default: 1 batch solve; 20 for config2)")
+                    help="untimed steps first (default: 1 batch solve; 20 for a single matrix)")
     ap.add_argument("--plain-steps", type=int, default=None,
                     help="timed solves of the plain per-matrix path (default: --steps)")
     ap.add_argument("--eager-steps", type=int, default=2,
@@ -778,7 +822,8 @@ def main():
                          "pass (no 4-stream, subset or single-matrix figures; for kernel traces)")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of the oracle on the host (batch workload)")
-    ap.add_argument("--workload", default="config4", choices=["config4", "config2", "config5"],
+    ap.add_argument("--workload", default="config4",
+                    choices=["config4", "config1", "config2", "config3", "config5"],
                     help="config4: the batch of 4096 uneven matrices, batched against plain "
                          "(default); config2: the 12x12 trivariate matrix; config5: serving")
     ap.add_argument("--batch-count", type=int, default=4096)
@@ -812,7 +857,7 @@ def main():
     if args.cpu_single_core:
         cpu_single_core(args)
         return
-    single = args.workload == "config2"
+    single = args.workload in SINGLE_WORKLOADS
     if args.steps is None:
         args.steps = 200 if single else 5
     if args.warmup is None:
