@@ -40,5 +40,11 @@ hipError_t run_det_slab(const MatPlan& P, uint8_t* ws, int slab, hipStream_t st)
 hipError_t run_finalize(const MatPlan& P, uint8_t* ws, hipStream_t st);
 hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st);
 hipError_t run_reconstruct(const MatPlan& P, uint8_t* ws, uint32_t* out, hipStream_t st);
+// S4 and S5 together: the last interpolation pass also reconstructs the coefficients it
+// produces (and stores their residues as S4 does), one launch fewer; run_interpolate then
+// run_reconstruct where the pass's tiles for every prime do not fit in LDS or there is a
+// single variable.
+hipError_t run_interpolate_reconstruct(const MatPlan& P, uint8_t* ws, uint32_t* out,
+                                       hipStream_t st);
 
 }  // namespace pd

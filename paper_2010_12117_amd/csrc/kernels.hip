@@ -512,18 +512,19 @@ __device__ __forceinline__ void garner_load(GarnerShared<PN>& s, int pn, int L,
   }
 }
 
+// Coefficient c from its residues r[i] (Montgomery form, i < pn), written as L limbs at out.
 template <int PN>
-__device__ __forceinline__ void garner_body(const GarnerShared<PN>& s,
-                                            const uint32_t* __restrict__ coef,
-                                            uint32_t* __restrict__ out, int64_t c, int64_t C,
-                                            int pn, int L) {
+__device__ __forceinline__ void garner_residues(const GarnerShared<PN>& s,
+                                                const uint32_t (&r)[PN],
+                                                uint32_t* __restrict__ out, int64_t c, int pn,
+                                                int L) {
   uint32_t alpha[PN];
 #pragma unroll
   for (int i = 0; i < PN; ++i) {
     if (i < pn) {
       const uint32_t p = s.p[i], pinv = s.pinv[i];
       // residue out of Montgomery form and divided by G (the inverse-DFT factor)
-      const uint32_t x = mm(coef[(int64_t)i * C + c], s.scale[i], p, pinv);
+      const uint32_t x = mm(r[i], s.scale[i], p, pinv);
       uint32_t acc = 0u;
 #pragma unroll
       for (int j = 0; j < PN; ++j) {
@@ -572,6 +573,121 @@ __device__ __forceinline__ void garner_body(const GarnerShared<PN>& s,
 #pragma unroll
   for (int l = 0; l < PN; ++l) {
     if (l < L) o[l] = X[l];
+  }
+}
+
+template <int PN>
+__device__ __forceinline__ void garner_body(const GarnerShared<PN>& s,
+                                            const uint32_t* __restrict__ coef,
+                                            uint32_t* __restrict__ out, int64_t c, int64_t C,
+                                            int pn, int L) {
+  uint32_t r[PN];
+#pragma unroll
+  for (int i = 0; i < PN; ++i) r[i] = i < pn ? coef[(int64_t)i * C + c] : 0u;
+  garner_residues<PN>(s, r, out, c, pn, L);
+}
+
+// ------------------------------------------------------------------------------------
+// S4 (last pass) + S5 in one launch: a block takes W lines of the last variable for every
+// prime (lines along the last variable are contiguous: inner = 1), runs each prime's inverse
+// transform in LDS as intt_body does, stores the trimmed coefficient residues where S4 puts
+// them (so that S5 can be run again from them), and reconstructs the block's coefficients from
+// the residues still in LDS. Tile of prime q: [Nv][W] in bit-reversed rows, then its Nv/2
+// twiddles w^{-t}, at q * (Nv W + Nv/2) words.
+// ------------------------------------------------------------------------------------
+template <int PN>
+__global__ __launch_bounds__(kBlock) void intt_garner_kernel(
+    const uint32_t* __restrict__ in, uint32_t* __restrict__ coef, uint32_t* __restrict__ out,
+    int64_t outer, int Nv, int logN, int Dv1, int W, int pn, int L,
+    const uint32_t* __restrict__ itw, int64_t tw_stride, const PrimeConst* __restrict__ pcs,
+    const uint32_t* __restrict__ gw, const uint32_t* __restrict__ gc,
+    const uint32_t* __restrict__ mlimbs, const uint32_t* __restrict__ hlimbs) {
+  __shared__ GarnerShared<PN> s;
+  extern __shared__ uint32_t tiles[];
+  const int per = Nv * W + Nv / 2;  // words per prime
+  const int total = Nv * W;
+  const int lW = __builtin_ctz((unsigned)W);
+  const int64_t line0 = (int64_t)blockIdx.x * W;
+  const int nW = (int)((outer - line0) < W ? (outer - line0) : W);
+  garner_load<PN>(s, pn, L, pcs, gw, gc, mlimbs, hlimbs);
+  for (int t = threadIdx.x; t < pn * (Nv / 2); t += kBlock) {
+    const int q = t / (Nv / 2), i = t - q * (Nv / 2);
+    tiles[q * per + total + i] = itw[(int64_t)q * tw_stride + i];
+  }
+  // load: element j of local line l of prime q goes to row brev(j), column l
+  for (int idx = threadIdx.x; idx < pn * total; idx += kBlock) {
+    const int q = idx / total, r = idx - q * total;
+    const int l = r >> logN, j = r & (Nv - 1);
+    uint32_t v = 0u;
+    if (l < nW) v = in[((int64_t)q * outer + line0 + l) * Nv + j];
+    const int rj = logN ? (int)(__brev((unsigned)j) >> (32 - logN)) : 0;
+    tiles[q * per + rj * W + l] = v;
+  }
+  __syncthreads();
+  int st = 1;
+  for (; st + 1 <= logN; st += 2) {  // two radix-2 stages per pass (intt_body)
+    const int h = 1 << (st - 1);
+    const int st1 = Nv >> st, st2 = Nv >> (st + 1);
+    const int quarter = (Nv / 4) * W;
+    for (int bi = threadIdx.x; bi < pn * quarter; bi += kBlock) {
+      const int q = bi / quarter, bq = bi - q * quarter;
+      const uint32_t p = s.p[q], pinv = s.pinv[q];
+      uint32_t* tile = tiles + q * per;
+      const uint32_t* twl = tile + total;
+      const int l = bq & (W - 1);
+      const int b = bq >> lW;
+      const int grp = b >> (st - 1), pos = b & (h - 1);
+      const int i0 = grp * 4 * h + pos;
+      uint32_t* e0 = tile + i0 * W + l;
+      const uint32_t x0 = e0[0], x1 = e0[h * W], x2 = e0[2 * h * W], x3 = e0[3 * h * W];
+      const uint32_t t1 = twl[pos * st1];
+      const uint32_t v1 = mm(x1, t1, p, pinv), v3 = mm(x3, t1, p, pinv);
+      const uint32_t u0 = addm(x0, v1, p), u1 = subm(x0, v1, p);
+      const uint32_t u2 = addm(x2, v3, p), u3 = subm(x2, v3, p);
+      const uint32_t y2 = mm(u2, twl[pos * st2], p, pinv);
+      const uint32_t y3 = mm(u3, twl[(pos + h) * st2], p, pinv);
+      e0[0] = addm(u0, y2, p);
+      e0[2 * h * W] = subm(u0, y2, p);
+      e0[h * W] = addm(u1, y3, p);
+      e0[3 * h * W] = subm(u1, y3, p);
+    }
+    __syncthreads();
+  }
+  for (; st <= logN; ++st) {  // the last stage when log2 Nv is odd
+    const int half = 1 << (st - 1);
+    const int stride = Nv >> st;
+    const int halfw = (Nv / 2) * W;
+    for (int bi = threadIdx.x; bi < pn * halfw; bi += kBlock) {
+      const int q = bi / halfw, bq = bi - q * halfw;
+      const uint32_t p = s.p[q], pinv = s.pinv[q];
+      uint32_t* tile = tiles + q * per;
+      const uint32_t* twl = tile + total;
+      const int l = bq & (W - 1);
+      const int b = bq >> lW;
+      const int grp = b >> (st - 1), pos = b & (half - 1);
+      const int i0 = grp * 2 * half + pos, i1 = i0 + half;
+      const uint32_t u = tile[i0 * W + l];
+      const uint32_t v = mm(tile[i1 * W + l], twl[pos * stride], p, pinv);
+      tile[i0 * W + l] = addm(u, v, p);
+      tile[i1 * W + l] = subm(u, v, p);
+    }
+    __syncthreads();
+  }
+  // the coefficient residues (S4's output) and the reconstruction (S5) of each coefficient
+  const int64_t C = outer * Dv1;
+  for (int idx = threadIdx.x; idx < nW * Dv1; idx += kBlock) {
+    const int l = idx / Dv1, e = idx - l * Dv1;
+    const int64_t c = (line0 + l) * Dv1 + e;
+    uint32_t r[PN];
+#pragma unroll
+    for (int q = 0; q < PN; ++q) {
+      r[q] = 0u;
+      if (q < pn) {
+        r[q] = tiles[q * per + e * W + l];
+        coef[(int64_t)q * C + c] = r[q];
+      }
+    }
+    garner_residues<PN>(s, r, out, c, pn, L);
   }
 }
 
@@ -917,12 +1033,14 @@ hipError_t run_finalize(const MatPlan& P, uint8_t* ws, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
-  if (P.k == 0) return hipSuccess;
+// The interpolation passes over the variables 0 .. vhi in order (the first pass divides; the
+// pass over variable v writes iA for even v and iB for odd v, the last variable's pass the
+// coefficient region).
+hipError_t run_interpolate_passes(const MatPlan& P, uint8_t* ws, int vhi, hipStream_t st) {
   const uint32_t* in = (const uint32_t*)(ws + P.off_detv);
   uint32_t* bufs[2] = {(uint32_t*)(ws + P.off_iA), (uint32_t*)(ws + P.off_iB)};
   int which = 0;
-  for (int v = 0; v < P.k; ++v) {
+  for (int v = 0; v <= vhi; ++v) {
     int64_t outer = 1, inner = 1;
     for (int u = 0; u < v; ++u) outer *= P.D[u] + 1;
     for (int u = v + 1; u < P.k; ++u) inner *= P.N[u];
@@ -949,6 +1067,59 @@ hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
     which ^= 1;
   }
   return hipSuccess;
+}
+
+hipError_t run_interpolate(const MatPlan& P, uint8_t* ws, hipStream_t st) {
+  if (P.k == 0) return hipSuccess;
+  return run_interpolate_passes(P, ws, P.k - 1, st);
+}
+
+// Bytes of LDS for the tiles of intt_garner_kernel (every prime's W lines of N values and its
+// N/2 twiddles) and the largest such size it takes.
+constexpr size_t kInttGarnerLds = 40 * 1024;
+size_t intt_garner_lds(int pn, int Nv, int W) {
+  return (size_t)pn * ((size_t)Nv * W + Nv / 2) * sizeof(uint32_t);
+}
+
+template <int PN>
+hipError_t launch_intt_garner(const MatPlan& P, const uint32_t* in, uint32_t* coef, uint32_t* out,
+                              int64_t outer, int Nv, int logN, int W, hipStream_t st) {
+  const int v = P.k - 1;
+  const int64_t blocks = (outer + W - 1) / W;
+  hipLaunchKernelGGL((intt_garner_kernel<PN>), dim3((unsigned)blocks), dim3(kBlock),
+                     intt_garner_lds(P.pn, Nv, W), st, in, coef, out, outer, Nv, logN, P.D[v] + 1,
+                     W, P.pn, P.L, P.d_itw + P.tw_off[v], P.tw_stride, P.d_pc, P.d_gw, P.d_gc,
+                     P.d_mlimbs, P.d_hlimbs);
+  return hipGetLastError();
+}
+
+hipError_t run_interpolate_reconstruct(const MatPlan& P, uint8_t* ws, uint32_t* out,
+                                       hipStream_t st) {
+  const int v = P.k - 1;
+  // the last pass by itself: no variables, one variable (its pass also divides), or tiles
+  // that do not fit
+  if (P.k < 2 || intt_garner_lds(P.pn, P.N[v], 1) > kInttGarnerLds) {
+    hipError_t err = run_interpolate(P, ws, st);
+    return err != hipSuccess ? err : run_reconstruct(P, ws, out, st);
+  }
+  hipError_t err = run_interpolate_passes(P, ws, v - 1, st);
+  if (err != hipSuccess) return err;
+  int64_t outer = 1;
+  for (int u = 0; u < v; ++u) outer *= P.D[u] + 1;
+  const int Nv = P.N[v];
+  int logN = 0;
+  while ((1 << logN) < Nv) ++logN;
+  // lines per block: a power of two, while at least 512 blocks remain and the tiles fit
+  int W = 1;
+  while (2 * W * Nv <= kTileElems && (outer + 2 * W - 1) / (2 * W) >= 512 &&
+         intt_garner_lds(P.pn, Nv, 2 * W) <= kInttGarnerLds)
+    W <<= 1;
+  // input: the output of the pass over variable v - 1 (passes alternate iA, iB)
+  const uint32_t* in = (const uint32_t*)(ws + ((v - 1) % 2 == 0 ? P.off_iA : P.off_iB));
+  uint32_t* coef = (uint32_t*)(ws + P.off_coef);
+  if (P.pn <= 8) return launch_intt_garner<8>(P, in, coef, out, outer, Nv, logN, W, st);
+  if (P.pn <= 16) return launch_intt_garner<16>(P, in, coef, out, outer, Nv, logN, W, st);
+  return launch_intt_garner<32>(P, in, coef, out, outer, Nv, logN, W, st);
 }
 
 hipError_t run_reconstruct(const MatPlan& P, uint8_t* ws, uint32_t* out, hipStream_t st) {

@@ -344,6 +344,12 @@ polydet_status run_stages(const pd::MatPlan& P, int b, int e, const int64_t* d_c
       s = 1;
       continue;
     }
+    if (s == 4 && e == POLYDET_NUM_STAGES && !ev) {
+      // S4 and S5 in one go: the last interpolation pass reconstructs the coefficients too
+      if ((err = pd::run_interpolate_reconstruct(P, ws, d_out, st)) != hipSuccess)
+        return hip_fail(err, "interpolate and reconstruct");
+      break;
+    }
     if ((err = run_stage(P, s, d_coeffs, d_out, ws, st)) != hipSuccess)
       return hip_fail(err, kStageNames[s]);
     if (ev && (err = hipEventRecord(ev[s + 1], st)) != hipSuccess)
