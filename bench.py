@@ -9,7 +9,8 @@ replayed; the plain path solves the same matrices one by one with the single-mat
 The metric is modular determinants per second (prime x grid point, summed over the batch),
 whole job; exact polynomial determinants per second and the batched/plain ratio are reported
 beside it. The line also carries the 12 x 12 trivariate single-matrix workload's kernel
-roofline (`roofline_config2`).
+roofline (`roofline_config2`) and the times of the 4 x 4 bivariate and 22 x 22 Sylvester
+matrices alone (`single_matrix`).
 
 Prints one JSON line (the repository's benchmark contract). Other modes:
   --workload config1   the single 4 x 4 bivariate matrix (16^2 grid, 1 prime; launch-bound)
@@ -471,6 +472,8 @@ def bench_batch(args):
         progress("batch done; 12x12 trivariate roofline")
         c2, (arr2, info2) = config2_roofline()
         line["roofline_config2"] = c2
+        progress("the 4x4 bivariate and 22x22 Sylvester matrices")
+        line["single_matrix"] = {w: single_summary(w) for w in ("config1", "config3")}
     if not args.no_cpu_baseline:
         progress("oracle on the host")
         line["cpu_baseline"] = cpu_baseline_batch(mats, infos, args.cpu_budget)
@@ -577,7 +580,26 @@ def graph_replay_ms(pl, d, out, ws, reps):
 
 def bench_single(args):
     """One matrix alone: the 4 x 4 bivariate (config1), 12 x 12 trivariate (config2) or 22 x 22
-    Sylvester (config3) workload."""
+    Sylvester (config3) workload; prints its JSON line."""
+    print(json.dumps(single_line(args)), flush=True)
+
+
+def single_summary(workload, steps=50):
+    """The main figures of a single-matrix workload's line (no CPU baseline), for the batch
+    line."""
+    import types
+    a = types.SimpleNamespace(workload=workload, det_lanes=None, det_form="auto",
+                              calibrate_copy=False, warmup=5, steps=steps, no_cpu_baseline=True)
+    d = single_line(a)
+    return {"workload": d["config"]["workload"], "solves": steps,
+            "ms_per_solve": d["ms_per_step"], "ms_per_solve_median": d["ms_per_step_median"],
+            "ms_per_solve_graph": d["ms_per_step_graph"], "modular_dets_per_s": d["value"],
+            "exact_dets_per_s": d["exact_dets_per_s"], "stage_kernel_ms": d["stage_kernel_ms"],
+            "roofline_frac": d["roofline"]["frac"], "det_kernel": d["roofline"]["kernel"]}
+
+
+def single_line(args):
+    """The JSON line of one single-matrix workload (bench_single)."""
     import numpy as np
     import torch
 
@@ -655,7 +677,7 @@ def bench_single(args):
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_single(arr, PL.det_degree_bound_from_shape(n, deg),
                                                    pn, G)
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def bench_serving(args):

@@ -342,6 +342,54 @@ def test_config3b_resultant_closed_form():
     assert box_to_dict(got) == expect
 
 
+# shapes for the reduction folded into the first evaluation pass and the reconstruction folded
+# into the last interpolation pass: last variables of degree 0, a 1 x 1 grid, three variables,
+# the reconstruction's 16- and 32-prime forms (10 primes from the bound, 20 forced)
+FOLD_CASES = [(4, (2, 0), 10 ** 6, 31, 0), (3, (0, 0), 10 ** 6, 32, 0),
+              (5, (1, 0, 2), 10 ** 3, 33, 0), (6, (3, 1), 2 ** 45, 34, 0), (4, (2, 1), 10, 35, 20)]
+
+
+def check_against_stages(arr, pl, ref):
+    """The plan run one stage at a time (separate reduction, interpolation passes and
+    reconstruction) gives the solve's limbs `ref`."""
+    import torch
+    d = torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+    ws = torch.empty(pl.info["workspace_bytes"], dtype=torch.uint8, device="cuda")
+    out = torch.full_like(ref, -1)
+    for s in range(6):
+        pdm.solve_stages_device(pl, s, s + 1, d if s == 0 else None, out if s == 5 else None, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("n,deg,amp,seed,force", FOLD_CASES)
+def test_folded_reduction_and_reconstruction(n, deg, amp, seed, force):
+    # the solve (folded launches) against the oracle and against the same plan stage by stage
+    import torch
+    arr = W.random_matrix(np.random.default_rng(seed), n, deg, -amp, amp, zero_prob=0.2)
+    got, pl, _ = gpu_solve(arr, flags=pdm.FORCE_PN(force) if force else 0)
+    if force:
+        assert pl.info["pn"] == force
+    assert box_to_dict(got) == box_to_dict(oracle_box(arr))
+    ref, _ = pdm.solve_device(pl, torch.from_numpy(np.ascontiguousarray(arr)).cuda())
+    check_against_stages(arr, pl, ref)
+
+
+def test_reconstruction_tiles_beyond_lds():
+    # 28 primes over a last-variable grid of 256: the folded pass's tiles (28 x 384 words) do
+    # not fit its LDS, so the last pass and the reconstruction run as separate launches; the
+    # result equals the folded solve with 8 primes (the primes beyond the bound's need change
+    # nothing) and the stage-by-stage run
+    import torch
+    arr = W.random_matrix(np.random.default_rng(44), 5, (1, 31), -10, 10, zero_prob=0.2)
+    a, pla, _ = gpu_solve(arr, flags=pdm.FORCE_PN(28))
+    b, plb, _ = gpu_solve(arr, flags=pdm.FORCE_PN(8))
+    assert pla.info["N"][-1] == 256 and 28 * (256 + 128) * 4 > 40 * 1024 >= 8 * (256 + 128) * 4
+    assert box_to_dict(a) == box_to_dict(b)
+    ref, _ = pdm.solve_device(pla, torch.from_numpy(np.ascontiguousarray(arr)).cuda())
+    check_against_stages(arr, pla, ref)
+
+
 def _large_order_cases():
     import os
     import sys
