@@ -53,7 +53,7 @@ extern "C" {
 typedef enum polydet_status {
   POLYDET_OK = 0,
   POLYDET_EINVAL = 1,        /* bad argument, shape or buffer size */
-  POLYDET_EUNSUPPORTED = 2,  /* beyond this build's limits (see polydet_limits) */
+  POLYDET_EUNSUPPORTED = 2,  /* beyond the library's limits (see polydet_limits) */
   POLYDET_ENOMEM = 3,        /* host or device allocation failed */
   POLYDET_EDEVICE = 4,       /* HIP error; message in polydet_last_error() */
   POLYDET_ECANCELLED = 5
@@ -305,7 +305,7 @@ const char* polydet_status_string(polydet_status status);
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char* polydet_last_error(void);
 
-/* Limits of this build: maximum n, nvars, N[v] and pn. Any pointer may be NULL. */
+/* Limits of the library: maximum n, nvars, N[v] and pn. Any pointer may be NULL. */
 /* Launch-mapping table for the elimination kernel, per class c and matrix order n (1..32;
  * index 0 is unused). Class 0: the first variable has 2 to 4 coefficients (its evaluation is
  * paired across the wave's halves, two terms per lane); class 1: any other matrix with at

@@ -696,7 +696,7 @@ const char* polydet_status_string(polydet_status status) {
   switch (status) {
     case POLYDET_OK: return "ok";
     case POLYDET_EINVAL: return "invalid argument";
-    case POLYDET_EUNSUPPORTED: return "unsupported by this build";
+    case POLYDET_EUNSUPPORTED: return "beyond the library's limits";
     case POLYDET_ENOMEM: return "out of memory";
     case POLYDET_EDEVICE: return "device error";
     case POLYDET_ECANCELLED: return "cancelled";

@@ -65,7 +65,7 @@ def test_host_plan_matches_oracle_plan(which):
     assert info["limbs"] == PL.limbs_for(M)
 
 
-def test_survey_sizes():
+def test_workload_plan_sizes():
     # sizes of the paper-shaped workloads (grid, primes)
     c2 = pdm.plan(12, (3, 3, 3), host_coeffs=W.config2(), flags=pdm.HOST_ONLY).info
     assert c2["N"] == (64, 64, 64) and c2["pn"] == 7 and c2["ncoeff"] == 37 ** 3
