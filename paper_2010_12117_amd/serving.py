@@ -38,7 +38,7 @@ from __future__ import annotations
 import collections
 import threading
 import time
-from concurrent.futures import CancelledError, Future
+from concurrent.futures import CancelledError, Future, ThreadPoolExecutor
 from dataclasses import dataclass
 from typing import Deque, List
 
@@ -97,6 +97,10 @@ class Server:
     prime_chunk: primes per enqueued range (None: the whole solve at once).
     policy: "sjf" (shortest predicted first, with aging) or "fifo"."""
 
+    # None: the loop sleeps until a waiter thread reports a finished device step (_watch); a
+    # number: it polls _is_done that often instead (device stand-ins without events)
+    poll_s = None
+
     def __init__(self, memory_budget: int = 64 << 30, slots: int = 4, device: str = "cuda:0",
                  flags: int = 0, prime_chunk=None, policy: str = "sjf",
                  starve_factor: float = 4.0, starve_floor_s: float = 0.05):
@@ -128,6 +132,8 @@ class Server:
         self.torch = torch
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        # one outstanding device step per running job: a waiter per slot (and spares)
+        self.waiters = ThreadPoolExecutor(max_workers=2 * slots, thread_name_prefix="polydet-wait")
 
     def _make_plan(self, coeffs, n, deg, max_workspace=None):
         return B.plan(n, deg, host_coeffs=coeffs, flags=self.flags, max_workspace=max_workspace)
@@ -164,8 +170,16 @@ class Server:
             job.host_out.copy_(d_out, non_blocking=True)
 
     def _record(self, job: _Job):
-        job.done_event = self.torch.cuda.Event()
+        # a blocking-sync event: its waiter sleeps until the step is done instead of spinning
+        job.done_event = self.torch.cuda.Event(blocking=True)
         job.done_event.record(self.streams[job.stream])
+        self.waiters.submit(self._watch, job.done_event)
+
+    def _watch(self, event):
+        # wakes the serving loop when the device step behind `event` has finished
+        event.synchronize()
+        with self.lock:
+            self.lock.notify()
 
     def _is_done(self, job: _Job) -> bool:
         return job.done_event.query()
@@ -230,6 +244,9 @@ class Server:
             self.lock.notify()
         if wait:
             self.thread.join()
+            waiters = getattr(self, "waiters", None)
+            if waiters is not None:
+                waiters.shutdown(wait=True)  # every recorded step has finished by now
 
     def stats(self) -> dict:
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
@@ -386,10 +403,10 @@ class Server:
                 self._admit()
                 if self.closed and not self.queue and not self.running:
                     return
-                if not self.running and not self.queue:
-                    self.lock.wait(timeout=0.05)
-            if self.running:
-                time.sleep(0.0002)
+                if not done:
+                    # until a waiter reports a finished step, a client submits or cancels, or
+                    # close() is called (or the polling interval of a stand-in passes)
+                    self.lock.wait(timeout=self.poll_s if self.poll_s else 0.05)
 
 
 def poisson_arrivals(rng: np.random.Generator, count: int, rate: float) -> np.ndarray:

@@ -22,6 +22,8 @@ class StubServer(S.Server):
     """Jobs are (n x n) int64 arrays; entry [0, 0] holds the job's simulated device time in
     ms, or a FAIL_* code; entry [0, 1] a tag recorded in completion order."""
 
+    poll_s = 0.0002  # simulated device time: no events to wait on, so the loop polls
+
     def __init__(self, *a, **kw):
         self.order = []
         self.gate = threading.Event()
