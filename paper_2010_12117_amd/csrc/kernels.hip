@@ -8,6 +8,7 @@
 // Every value below is a Montgomery representative (modarith.h) until the reconstruction.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <utility>
 
 #include "batch.h"
@@ -456,6 +457,124 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
       dst[(o * Dv1 + e) * inner + q] = tile[e * W + l];
     }
   }
+}
+
+// ------------------------------------------------------------------------------------
+// The same pass for lines of 64 points whose lines run along a contiguous axis (inner >= 32),
+// with the transform in registers: 64 = 8 x 8 (Cooley-Tukey). A block takes 32 lines of one
+// prime; thread (t, l), t < 8, l < 32, holds the points j = 8 i + t of line l (i < 8), takes
+// their 8-point transform (stride-8 decimation), multiplies entry k1 by w^{t k1}, exchanges
+// through LDS so that it holds entry k1 = t of all eight threads of its line, and takes the
+// 8-point transform over those: output e = t + 8 k2. One LDS exchange and one barrier per
+// pass, against log2(64)/2 barrier-separated stages in LDS (intt_body). With `den` the first
+// pass divides as intt_body does (eight points per thread, one exponentiation).
+// ------------------------------------------------------------------------------------
+constexpr int kInttRegLines = 32;
+
+// In-place 8-point transform a[k] <- sum_i a[i] r^{i k} with r a primitive 8th root of unity
+// (r1 = r, r2 = r^2, r3 = r^3, Montgomery form): decimation in frequency, whose outputs come
+// in bit-reversed order, which the static index permutation at the end undoes.
+__device__ __forceinline__ void dft8(uint32_t (&a)[8], uint32_t r1, uint32_t r2, uint32_t r3,
+                                     uint32_t p, uint32_t pinv) {
+  const uint32_t w4[4] = {0u, r1, r2, r3};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {  // span 4, twiddles r^i
+    const uint32_t u = a[i], v = a[i + 4];
+    a[i] = addm(u, v, p);
+    a[i + 4] = i == 0 ? subm(u, v, p) : mm(subm(u, v, p), w4[i], p, pinv);
+  }
+#pragma unroll
+  for (int h = 0; h < 8; h += 4) {  // span 2, twiddles r^{2 i}
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const uint32_t u = a[h + i], v = a[h + i + 2];
+      a[h + i] = addm(u, v, p);
+      a[h + i + 2] = i == 0 ? subm(u, v, p) : mm(subm(u, v, p), r2, p, pinv);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; i += 2) {  // span 1
+    const uint32_t u = a[i], v = a[i + 1];
+    a[i] = addm(u, v, p);
+    a[i + 1] = subm(u, v, p);
+  }
+  // a[p] holds the output bitrev3(p)
+  const uint32_t b1 = a[1], b3 = a[3];
+  a[1] = a[4];
+  a[3] = a[6];
+  a[4] = b1;
+  a[6] = b3;
+}
+
+__device__ __forceinline__ void intt64_body(uint32_t* xch, const uint32_t* __restrict__ in,
+                                            uint32_t* __restrict__ out, int64_t block,
+                                            int64_t outer, int64_t inner, int Dv1,
+                                            const uint32_t* __restrict__ itw, int64_t tw_stride,
+                                            const PrimeConst* __restrict__ pcs,
+                                            const uint32_t* __restrict__ den) {
+  constexpr int Nv = 64;
+  const int64_t lines = outer * inner;
+  const int64_t tiles_per_prime = lines / kInttRegLines;  // inner >= 32: lines % 32 == 0
+  const int prime = (int)(block / tiles_per_prime);
+  const int64_t line0 = (block - (int64_t)prime * tiles_per_prime) * kInttRegLines;
+  const int t = (int)(threadIdx.x >> 5), l = (int)(threadIdx.x & 31);
+  const uint32_t p = pcs[prime].p, pinv = pcs[prime].pinv;
+  const uint32_t* w = itw + (int64_t)prime * tw_stride;
+  const int64_t line = line0 + l;
+  const int lI = __builtin_ctzll((unsigned long long)inner);
+  const int64_t o = line >> lI, q = line & (inner - 1);
+  const uint32_t* src = in + (int64_t)prime * outer * Nv * inner + o * Nv * inner + q;
+  uint32_t v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = src[(int64_t)(8 * i + t) * inner];
+  // twiddles: w^{t k1} between the two transforms, and the 8th roots w^8, w^16, w^24
+  uint32_t tk[8];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) tk[k] = w[(t * k) & (Nv - 1)];
+  const uint32_t r1 = w[8], r2 = w[16], r3 = w[24];
+  if (den) {
+    const uint32_t one = pcs[prime].r1;
+    const uint32_t* dsrc = den + (src - in);
+    uint32_t d[8], pre[8];
+    uint32_t acc = one;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      d[i] = dsrc[(int64_t)(8 * i + t) * inner];
+      pre[i] = acc;  // product of the denominators before i
+      acc = mm(acc, d[i], p, pinv);
+    }
+    uint32_t inv = minv(acc, one, p, pinv);  // inverse of the product of all
+#pragma unroll
+    for (int i = 7; i >= 0; --i) {
+      const uint32_t di = mm(inv, pre[i], p, pinv);  // 1 / d[i]
+      inv = mm(inv, d[i], p, pinv);
+      v[i] = mm(v[i], di, p, pinv);
+    }
+  }
+  dft8(v, r1, r2, r3, p, pinv);  // over i: entry k1 of the inner transform (n2 = t)
+#pragma unroll
+  for (int k = 1; k < 8; ++k) v[k] = mm(v[k], tk[k], p, pinv);
+  // exchange: row (n2, k1) of 32 lines
+#pragma unroll
+  for (int k = 0; k < 8; ++k) xch[(t * 8 + k) * kInttRegLines + l] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int n2 = 0; n2 < 8; ++n2) v[n2] = xch[(n2 * 8 + t) * kInttRegLines + l];
+  dft8(v, r1, r2, r3, p, pinv);  // over n2: output e = t + 8 k2
+  uint32_t* dst = out + (int64_t)prime * outer * Dv1 * inner + o * Dv1 * inner + q;
+#pragma unroll
+  for (int k2 = 0; k2 < 8; ++k2) {
+    const int e = t + 8 * k2;
+    if (e < Dv1) dst[(int64_t)e * inner] = v[k2];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void intt64_kernel(
+    const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t outer, int64_t inner,
+    int Dv1, const uint32_t* __restrict__ itw, int64_t tw_stride,
+    const PrimeConst* __restrict__ pcs, const uint32_t* __restrict__ den) {
+  __shared__ uint32_t xch[64 * kInttRegLines];
+  intt64_body(xch, in, out, blockIdx.x, outer, inner, Dv1, itw, tw_stride, pcs, den);
 }
 
 __global__ __launch_bounds__(kBlock) void intt_kernel(
@@ -939,6 +1058,16 @@ int expand_outputs_per_thread(int Nv, int64_t inner, int m) {
   return NJ / nJB;
 }
 
+// Whether passes of 64 points along a contiguous axis take the register form (intt64_kernel);
+// POLYDET_INTT_REGISTERS=0 keeps the LDS-staged form everywhere (for comparisons).
+bool intt_register_form() {
+  static const bool on = [] {
+    const char* e = std::getenv("POLYDET_INTT_REGISTERS");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 int intt_lines_per_block(int64_t lines, int Nv, int pn) {
   // as many lines as fit in kTileElems, fewer while that leaves under ~1024 blocks (W stays
   // a power of two, so it divides inner when inner >= W). Measured at the 12x12 trivariate
@@ -1049,6 +1178,18 @@ hipError_t run_interpolate_passes(const MatPlan& P, uint8_t* ws, int vhi, hipStr
     int logN = 0;
     while ((1 << logN) < Nv) ++logN;
     const int64_t lines = outer * inner;
+    // the first pass also divides each point's numerator by its denominator
+    const uint32_t* den = v == 0 ? (const uint32_t*)(ws + P.off_den) : nullptr;
+    if (Nv == 64 && inner >= kInttRegLines && intt_register_form()) {
+      hipLaunchKernelGGL(intt64_kernel, dim3((unsigned)(lines / kInttRegLines * P.pn)),
+                         dim3(kBlock), 0, st, in, out, outer, inner, P.D[v] + 1,
+                         P.d_itw + P.tw_off[v], P.tw_stride, P.d_pc, den);
+      hipError_t err = hipGetLastError();
+      if (err != hipSuccess) return err;
+      in = out;
+      which ^= 1;
+      continue;
+    }
     int W = intt_lines_per_block(lines, Nv, P.pn);
     // the dividing first pass: enough lines that each thread has kFuseBatch points to invert
     // together (at 64^3 that halves the exponentiations; measured 2 us faster)
@@ -1056,8 +1197,6 @@ hipError_t run_interpolate_passes(const MatPlan& P, uint8_t* ws, int vhi, hipStr
       while (Nv * W < kFuseBatch * kBlock && Nv * (2 * W) <= kTileElems) W <<= 1;
     const int64_t tiles = (lines + W - 1) / W;
     const size_t lds = (size_t)(Nv * W + Nv / 2) * sizeof(uint32_t);
-    // the first pass also divides each point's numerator by its denominator
-    const uint32_t* den = v == 0 ? (const uint32_t*)(ws + P.off_den) : nullptr;
     hipLaunchKernelGGL(intt_kernel, dim3((unsigned)(tiles * P.pn)), dim3(kBlock), lds, st, in, out,
                        outer, Nv, logN, inner, P.D[v] + 1, W, P.d_itw + P.tw_off[v], P.tw_stride,
                        P.d_pc, den);
