@@ -53,7 +53,8 @@ struct BIntt {
   int64_t in_off, out_off, outer, inner, tw_stride, tiles;
   int64_t den_off;  // the first pass: the denominators, divided into the numerators as they load
                     // (-1 for the later passes)
-  int32_t pn, Nv, logN, Dv1, W, pad;
+  int32_t pn, Nv, logN, Dv1, W;
+  int32_t reg;      // the register form (intt64_body: 64 points, kInttRegLines lines a tile)
   const uint32_t* itw;
   const PrimeConst* pc;
 };

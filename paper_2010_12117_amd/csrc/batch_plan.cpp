@@ -269,8 +269,9 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, bool ha
         int logN = 0;
         while ((1 << logN) < Nv) ++logN;
         const int64_t lines = outer * inner;
-        int W = intt_lines_per_block(lines, Nv, P.pn);
-        if (v == 0)
+        const bool reg_form = intt_register_pass(Nv, inner);
+        int W = reg_form ? kInttRegLines : intt_lines_per_block(lines, Nv, P.pn);
+        if (v == 0 && !reg_form)
           while (Nv * W < kFuseBatch * 256 && Nv * (2 * W) <= kTileElems) W <<= 1;
         BIntt e{};
         e.block0 = vb;
@@ -286,11 +287,13 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, bool ha
         e.logN = logN;
         e.Dv1 = P.D[v] + 1;
         e.W = W;
+        e.reg = reg_form ? 1 : 0;
         e.itw = P.d_itw + P.tw_off[v];
         e.pc = P.d_pc;
         d.push_back(e);
         vb += e.tiles * P.pn;
-        lds = std::max(lds, (size_t)(Nv * W + Nv / 2) * 4);  // tile and twiddles
+        // tile and twiddles, or the register form's exchange rows
+        lds = std::max(lds, reg_form ? (size_t)Nv * kInttRegLines * 4 : (size_t)(Nv * W + Nv / 2) * 4);
       }
       if (d.empty()) continue;
       BLaunch L{};

@@ -12,6 +12,7 @@ constexpr int kTileElems = 8192;  // interpolation tile: at most 32 KB of LDS pe
                                   // the line's twiddles)
 constexpr int kFuseBatch = 8;     // denominators a thread of the first interpolation pass
                                   // inverts together (one exponentiation)
+constexpr int kInttRegLines = 32; // lines per block of the register-form 64-point pass
 
 // Whether an elimination kernel is compiled for this order and lanes-per-matrix.
 bool det_config_supported(int n, int lanes);
@@ -19,6 +20,9 @@ bool det_config_supported(int n, int lanes);
 // Launch shapes shared by the single and the batched paths.
 int expand_outputs_per_thread(int Nv, int64_t inner, int m);
 int intt_lines_per_block(int64_t lines, int Nv, int pn);
+// Whether an interpolation pass of Nv points per line, inner points apart, takes the register
+// form (64 points along an axis of at least kInttRegLines contiguous lines).
+bool intt_register_pass(int Nv, int64_t inner);
 int64_t finalize_threads(int64_t G, int pn);  // threads of the det = num / den launch
 
 hipError_t run_reduce(const MatPlan& P, const int64_t* coeffs, uint8_t* ws, hipStream_t st);

@@ -469,8 +469,6 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
 // pass, against log2(64)/2 barrier-separated stages in LDS (intt_body). With `den` the first
 // pass divides as intt_body does (eight points per thread, one exponentiation).
 // ------------------------------------------------------------------------------------
-constexpr int kInttRegLines = 32;
-
 // In-place 8-point transform a[k] <- sum_i a[i] r^{i k} with r a primitive 8th root of unity
 // (r1 = r, r2 = r^2, r3 = r^3, Montgomery form): decimation in frequency, whose outputs come
 // in bit-reversed order, which the static index permutation at the end undoes.
@@ -591,9 +589,13 @@ __global__ __launch_bounds__(kBlock) void intt_batch_kernel(const BIntt* __restr
   extern __shared__ uint32_t tile[];
   for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
     const BIntt& d = desc[find_desc(desc, ndesc, vb)];
-    intt_body(tile, (const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), vb - d.block0,
-              d.outer, d.Nv, d.logN, d.inner, d.Dv1, d.W, d.itw, d.tw_stride, d.pc,
-              d.den_off >= 0 ? (const uint32_t*)(ws + d.den_off) : nullptr);
+    const uint32_t* den = d.den_off >= 0 ? (const uint32_t*)(ws + d.den_off) : nullptr;
+    if (d.reg)
+      intt64_body(tile, (const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off),
+                  vb - d.block0, d.outer, d.inner, d.Dv1, d.itw, d.tw_stride, d.pc, den);
+    else
+      intt_body(tile, (const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), vb - d.block0,
+                d.outer, d.Nv, d.logN, d.inner, d.Dv1, d.W, d.itw, d.tw_stride, d.pc, den);
     __syncthreads();  // the next virtual block reuses the tile
   }
 }
@@ -1068,6 +1070,10 @@ bool intt_register_form() {
   return on;
 }
 
+bool intt_register_pass(int Nv, int64_t inner) {
+  return Nv == 64 && inner >= kInttRegLines && intt_register_form();
+}
+
 int intt_lines_per_block(int64_t lines, int Nv, int pn) {
   // as many lines as fit in kTileElems, fewer while that leaves under ~1024 blocks (W stays
   // a power of two, so it divides inner when inner >= W). Measured at the 12x12 trivariate
@@ -1180,7 +1186,7 @@ hipError_t run_interpolate_passes(const MatPlan& P, uint8_t* ws, int vhi, hipStr
     const int64_t lines = outer * inner;
     // the first pass also divides each point's numerator by its denominator
     const uint32_t* den = v == 0 ? (const uint32_t*)(ws + P.off_den) : nullptr;
-    if (Nv == 64 && inner >= kInttRegLines && intt_register_form()) {
+    if (intt_register_pass(Nv, inner)) {
       hipLaunchKernelGGL(intt64_kernel, dim3((unsigned)(lines / kInttRegLines * P.pn)),
                          dim3(kBlock), 0, st, in, out, outer, inner, P.D[v] + 1,
                          P.d_itw + P.tw_off[v], P.tw_stride, P.d_pc, den);
