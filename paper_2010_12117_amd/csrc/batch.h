@@ -54,7 +54,8 @@ struct BIntt {
   int64_t den_off;  // the first pass: the denominators, divided into the numerators as they load
                     // (-1 for the later passes)
   int32_t pn, Nv, logN, Dv1, W;
-  int32_t reg;      // the register form (intt64_body: 64 points, kInttRegLines lines a tile)
+  int32_t reg;      // the register form: Nv / 8 = 4, 8 or 16 (intt_reg_body, kInttRegLines
+                    // lines a tile), or 0
   const uint32_t* itw;
   const PrimeConst* pc;
 };

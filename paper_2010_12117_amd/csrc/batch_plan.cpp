@@ -269,7 +269,9 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, bool ha
         int logN = 0;
         while ((1 << logN) < Nv) ++logN;
         const int64_t lines = outer * inner;
-        const bool reg_form = intt_register_pass(Nv, inner);
+        // the register form up to 128 points (256 would raise the registers of every pass of
+        // the batched kernel, which holds all forms)
+        const bool reg_form = Nv <= 128 && intt_register_pass(Nv, inner);
         int W = reg_form ? kInttRegLines : intt_lines_per_block(lines, Nv, P.pn);
         if (v == 0 && !reg_form)
           while (Nv * W < kFuseBatch * 256 && Nv * (2 * W) <= kTileElems) W <<= 1;
@@ -287,7 +289,7 @@ std::string build_batch(const std::vector<MatPlan>& mats, size_t budget, bool ha
         e.logN = logN;
         e.Dv1 = P.D[v] + 1;
         e.W = W;
-        e.reg = reg_form ? 1 : 0;
+        e.reg = reg_form ? Nv / 8 : 0;
         e.itw = P.d_itw + P.tw_off[v];
         e.pc = P.d_pc;
         d.push_back(e);

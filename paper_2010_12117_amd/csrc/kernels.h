@@ -21,7 +21,7 @@ bool det_config_supported(int n, int lanes);
 int expand_outputs_per_thread(int Nv, int64_t inner, int m);
 int intt_lines_per_block(int64_t lines, int Nv, int pn);
 // Whether an interpolation pass of Nv points per line, inner points apart, takes the register
-// form (64 points along an axis of at least kInttRegLines contiguous lines).
+// form (32, 64, 128 or 256 points along an axis of at least kInttRegLines contiguous lines).
 bool intt_register_pass(int Nv, int64_t inner);
 int64_t finalize_threads(int64_t G, int pn);  // threads of the det = num / den launch
 

@@ -460,57 +460,56 @@ __device__ __forceinline__ void intt_body(uint32_t* tile, const uint32_t* __rest
 }
 
 // ------------------------------------------------------------------------------------
-// The same pass for lines of 64 points whose lines run along a contiguous axis (inner >= 32),
-// with the transform in registers: 64 = 8 x 8 (Cooley-Tukey). A block takes 32 lines of one
-// prime; thread (t, l), t < 8, l < 32, holds the points j = 8 i + t of line l (i < 8), takes
-// their 8-point transform (stride-8 decimation), multiplies entry k1 by w^{t k1}, exchanges
-// through LDS so that it holds entry k1 = t of all eight threads of its line, and takes the
-// 8-point transform over those: output e = t + 8 k2. One LDS exchange and one barrier per
-// pass, against log2(64)/2 barrier-separated stages in LDS (intt_body). With `den` the first
-// pass divides as intt_body does (eight points per thread, one exponentiation).
+// The same pass for lines of Nv = 8 M points (M = 4, 8, 16, 32) that run along a contiguous
+// axis (inner >= 32), with the transform in registers (Cooley-Tukey, Nv = M x 8). A block
+// takes 32 lines of one prime; thread (t, l), t < 8, l < 32, holds the points j = 8 i + t of
+// line l (i < M), takes their M-point transform (root w^8), multiplies entry k1 by w^{t k1},
+// and writes the entries to LDS; after one barrier it takes, for each k1 = t + 8 c < M, the
+// 8-point transform (root w^M) of entry k1 of the eight threads of its line: outputs
+// e = k1 + M k2. One LDS exchange and one barrier per pass, against log2(Nv)/2 barrier-
+// separated stages in LDS (intt_body). With `den` the first pass divides as intt_body does
+// (M points per thread share one exponentiation).
 // ------------------------------------------------------------------------------------
-// In-place 8-point transform a[k] <- sum_i a[i] r^{i k} with r a primitive 8th root of unity
-// (r1 = r, r2 = r^2, r3 = r^3, Montgomery form): decimation in frequency, whose outputs come
-// in bit-reversed order, which the static index permutation at the end undoes.
-__device__ __forceinline__ void dft8(uint32_t (&a)[8], uint32_t r1, uint32_t r2, uint32_t r3,
-                                     uint32_t p, uint32_t pinv) {
-  const uint32_t w4[4] = {0u, r1, r2, r3};
+
+// In-place M-point transform a[k] <- sum_i a[i] r^{i k}, r a primitive M-th root of unity, with
+// rt[i] = r^i (i < M/2, Montgomery form): decimation in frequency, whose outputs come in
+// bit-reversed order, which the static index permutation at the end undoes.
+template <int M>
+__device__ __forceinline__ void dft_reg(uint32_t (&a)[M], const uint32_t (&rt)[M / 2],
+                                        uint32_t p, uint32_t pinv) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {  // span 4, twiddles r^i
-    const uint32_t u = a[i], v = a[i + 4];
-    a[i] = addm(u, v, p);
-    a[i + 4] = i == 0 ? subm(u, v, p) : mm(subm(u, v, p), w4[i], p, pinv);
-  }
+  for (int span = M / 2; span >= 1; span >>= 1) {
+    const int step = (M / 2) / span;  // the twiddle of position i is r^{i step}
 #pragma unroll
-  for (int h = 0; h < 8; h += 4) {  // span 2, twiddles r^{2 i}
+    for (int blk = 0; blk < M; blk += 2 * span) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const uint32_t u = a[h + i], v = a[h + i + 2];
-      a[h + i] = addm(u, v, p);
-      a[h + i + 2] = i == 0 ? subm(u, v, p) : mm(subm(u, v, p), r2, p, pinv);
+      for (int i = 0; i < span; ++i) {
+        const uint32_t u = a[blk + i], v = a[blk + i + span];
+        a[blk + i] = addm(u, v, p);
+        a[blk + i + span] = i == 0 ? subm(u, v, p) : mm(subm(u, v, p), rt[i * step], p, pinv);
+      }
     }
   }
+  uint32_t b[M];
 #pragma unroll
-  for (int i = 0; i < 8; i += 2) {  // span 1
-    const uint32_t u = a[i], v = a[i + 1];
-    a[i] = addm(u, v, p);
-    a[i + 1] = subm(u, v, p);
+  for (int k = 0; k < M; ++k) {
+    int r = 0;
+#pragma unroll
+    for (int bit = 1; bit < M; bit <<= 1) r = (r << 1) | ((k & bit) ? 1 : 0);
+    b[k] = a[r];
   }
-  // a[p] holds the output bitrev3(p)
-  const uint32_t b1 = a[1], b3 = a[3];
-  a[1] = a[4];
-  a[3] = a[6];
-  a[4] = b1;
-  a[6] = b3;
+#pragma unroll
+  for (int k = 0; k < M; ++k) a[k] = b[k];
 }
 
-__device__ __forceinline__ void intt64_body(uint32_t* xch, const uint32_t* __restrict__ in,
-                                            uint32_t* __restrict__ out, int64_t block,
-                                            int64_t outer, int64_t inner, int Dv1,
-                                            const uint32_t* __restrict__ itw, int64_t tw_stride,
-                                            const PrimeConst* __restrict__ pcs,
-                                            const uint32_t* __restrict__ den) {
-  constexpr int Nv = 64;
+template <int M>
+__device__ __forceinline__ void intt_reg_body(uint32_t* xch, const uint32_t* __restrict__ in,
+                                              uint32_t* __restrict__ out, int64_t block,
+                                              int64_t outer, int64_t inner, int Dv1,
+                                              const uint32_t* __restrict__ itw, int64_t tw_stride,
+                                              const PrimeConst* __restrict__ pcs,
+                                              const uint32_t* __restrict__ den) {
+  constexpr int Nv = 8 * M;
   const int64_t lines = outer * inner;
   const int64_t tiles_per_prime = lines / kInttRegLines;  // inner >= 32: lines % 32 == 0
   const int prime = (int)(block / tiles_per_prime);
@@ -521,58 +520,65 @@ __device__ __forceinline__ void intt64_body(uint32_t* xch, const uint32_t* __res
   const int64_t line = line0 + l;
   const int lI = __builtin_ctzll((unsigned long long)inner);
   const int64_t o = line >> lI, q = line & (inner - 1);
-  const uint32_t* src = in + (int64_t)prime * outer * Nv * inner + o * Nv * inner + q;
-  uint32_t v[8];
+  const int64_t base = (int64_t)prime * outer * Nv * inner + o * Nv * inner + q;
+  uint32_t v[M];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) v[i] = src[(int64_t)(8 * i + t) * inner];
-  // twiddles: w^{t k1} between the two transforms, and the 8th roots w^8, w^16, w^24
-  uint32_t tk[8];
+  for (int i = 0; i < M; ++i) v[i] = in[base + (int64_t)(8 * i + t) * inner];
+  uint32_t rin[M / 2];  // roots of the inner transform: w^{8 i}
 #pragma unroll
-  for (int k = 1; k < 8; ++k) tk[k] = w[(t * k) & (Nv - 1)];
-  const uint32_t r1 = w[8], r2 = w[16], r3 = w[24];
+  for (int i = 0; i < M / 2; ++i) rin[i] = w[8 * i];
   if (den) {
     const uint32_t one = pcs[prime].r1;
-    const uint32_t* dsrc = den + (src - in);
-    uint32_t d[8], pre[8];
+    uint32_t d[M], pre[M];
     uint32_t acc = one;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      d[i] = dsrc[(int64_t)(8 * i + t) * inner];
+    for (int i = 0; i < M; ++i) {
+      d[i] = den[base + (int64_t)(8 * i + t) * inner];
       pre[i] = acc;  // product of the denominators before i
       acc = mm(acc, d[i], p, pinv);
     }
     uint32_t inv = minv(acc, one, p, pinv);  // inverse of the product of all
 #pragma unroll
-    for (int i = 7; i >= 0; --i) {
+    for (int i = M - 1; i >= 0; --i) {
       const uint32_t di = mm(inv, pre[i], p, pinv);  // 1 / d[i]
       inv = mm(inv, d[i], p, pinv);
       v[i] = mm(v[i], di, p, pinv);
     }
   }
-  dft8(v, r1, r2, r3, p, pinv);  // over i: entry k1 of the inner transform (n2 = t)
+  dft_reg<M>(v, rin, p, pinv);  // over i: entry k1 of the inner transform (n2 = t)
 #pragma unroll
-  for (int k = 1; k < 8; ++k) v[k] = mm(v[k], tk[k], p, pinv);
+  for (int k = 1; k < M; ++k) v[k] = mm(v[k], w[(t * k) & (Nv - 1)], p, pinv);
   // exchange: row (n2, k1) of 32 lines
 #pragma unroll
-  for (int k = 0; k < 8; ++k) xch[(t * 8 + k) * kInttRegLines + l] = v[k];
+  for (int k = 0; k < M; ++k) xch[(t * M + k) * kInttRegLines + l] = v[k];
   __syncthreads();
+  const uint32_t rout[4] = {w[0], w[M], w[2 * M], w[3 * M]};  // the 8th roots w^{M j}
 #pragma unroll
-  for (int n2 = 0; n2 < 8; ++n2) v[n2] = xch[(n2 * 8 + t) * kInttRegLines + l];
-  dft8(v, r1, r2, r3, p, pinv);  // over n2: output e = t + 8 k2
-  uint32_t* dst = out + (int64_t)prime * outer * Dv1 * inner + o * Dv1 * inner + q;
+  for (int c = 0; c < (M + 7) / 8; ++c) {
+    const int k1 = t + 8 * c;
+    if (k1 < M) {
+      uint32_t z[8];
 #pragma unroll
-  for (int k2 = 0; k2 < 8; ++k2) {
-    const int e = t + 8 * k2;
-    if (e < Dv1) dst[(int64_t)e * inner] = v[k2];
+      for (int n2 = 0; n2 < 8; ++n2) z[n2] = xch[(n2 * M + k1) * kInttRegLines + l];
+      dft_reg<8>(z, rout, p, pinv);  // over n2: output e = k1 + M k2
+      uint32_t* dst = out + (int64_t)prime * outer * Dv1 * inner + o * Dv1 * inner + q;
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) {
+        const int e = k1 + M * k2;
+        if (e < Dv1) dst[(int64_t)e * inner] = z[k2];
+      }
+    }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void intt64_kernel(
+// The register-form pass for Nv = 8 M (intt_reg_body); xch holds Nv x 32 words.
+template <int M>
+__global__ __launch_bounds__(kBlock) void intt_reg_kernel(
     const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t outer, int64_t inner,
     int Dv1, const uint32_t* __restrict__ itw, int64_t tw_stride,
     const PrimeConst* __restrict__ pcs, const uint32_t* __restrict__ den) {
-  __shared__ uint32_t xch[64 * kInttRegLines];
-  intt64_body(xch, in, out, blockIdx.x, outer, inner, Dv1, itw, tw_stride, pcs, den);
+  __shared__ uint32_t xch[8 * M * kInttRegLines];
+  intt_reg_body<M>(xch, in, out, blockIdx.x, outer, inner, Dv1, itw, tw_stride, pcs, den);
 }
 
 __global__ __launch_bounds__(kBlock) void intt_kernel(
@@ -590,9 +596,15 @@ __global__ __launch_bounds__(kBlock) void intt_batch_kernel(const BIntt* __restr
   for (int64_t vb = blockIdx.x; vb < vblocks; vb += gridDim.x) {
     const BIntt& d = desc[find_desc(desc, ndesc, vb)];
     const uint32_t* den = d.den_off >= 0 ? (const uint32_t*)(ws + d.den_off) : nullptr;
-    if (d.reg)
-      intt64_body(tile, (const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off),
-                  vb - d.block0, d.outer, d.inner, d.Dv1, d.itw, d.tw_stride, d.pc, den);
+    const uint32_t* src = (const uint32_t*)(ws + d.in_off);
+    uint32_t* dst = (uint32_t*)(ws + d.out_off);
+    const int64_t b = vb - d.block0;
+    if (d.reg == 4)
+      intt_reg_body<4>(tile, src, dst, b, d.outer, d.inner, d.Dv1, d.itw, d.tw_stride, d.pc, den);
+    else if (d.reg == 8)
+      intt_reg_body<8>(tile, src, dst, b, d.outer, d.inner, d.Dv1, d.itw, d.tw_stride, d.pc, den);
+    else if (d.reg == 16)
+      intt_reg_body<16>(tile, src, dst, b, d.outer, d.inner, d.Dv1, d.itw, d.tw_stride, d.pc, den);
     else
       intt_body(tile, (const uint32_t*)(ws + d.in_off), (uint32_t*)(ws + d.out_off), vb - d.block0,
                 d.outer, d.Nv, d.logN, d.inner, d.Dv1, d.W, d.itw, d.tw_stride, d.pc, den);
@@ -1060,8 +1072,9 @@ int expand_outputs_per_thread(int Nv, int64_t inner, int m) {
   return NJ / nJB;
 }
 
-// Whether passes of 64 points along a contiguous axis take the register form (intt64_kernel);
-// POLYDET_INTT_REGISTERS=0 keeps the LDS-staged form everywhere (for comparisons).
+// Whether passes of 32-256 points along a contiguous axis take the register form
+// (intt_reg_kernel); POLYDET_INTT_REGISTERS=0 keeps the LDS-staged form everywhere (for
+// comparisons).
 bool intt_register_form() {
   static const bool on = [] {
     const char* e = std::getenv("POLYDET_INTT_REGISTERS");
@@ -1071,7 +1084,8 @@ bool intt_register_form() {
 }
 
 bool intt_register_pass(int Nv, int64_t inner) {
-  return Nv == 64 && inner >= kInttRegLines && intt_register_form();
+  return (Nv == 32 || Nv == 64 || Nv == 128 || Nv == 256) && inner >= kInttRegLines &&
+         intt_register_form();
 }
 
 int intt_lines_per_block(int64_t lines, int Nv, int pn) {
@@ -1187,9 +1201,21 @@ hipError_t run_interpolate_passes(const MatPlan& P, uint8_t* ws, int vhi, hipStr
     // the first pass also divides each point's numerator by its denominator
     const uint32_t* den = v == 0 ? (const uint32_t*)(ws + P.off_den) : nullptr;
     if (intt_register_pass(Nv, inner)) {
-      hipLaunchKernelGGL(intt64_kernel, dim3((unsigned)(lines / kInttRegLines * P.pn)),
-                         dim3(kBlock), 0, st, in, out, outer, inner, P.D[v] + 1,
-                         P.d_itw + P.tw_off[v], P.tw_stride, P.d_pc, den);
+      const dim3 g((unsigned)(lines / kInttRegLines * P.pn));
+      const int Dv1 = P.D[v] + 1;
+      const uint32_t* itw = P.d_itw + P.tw_off[v];
+      if (Nv == 32)
+        hipLaunchKernelGGL(intt_reg_kernel<4>, g, dim3(kBlock), 0, st, in, out, outer, inner, Dv1,
+                           itw, P.tw_stride, P.d_pc, den);
+      else if (Nv == 64)
+        hipLaunchKernelGGL(intt_reg_kernel<8>, g, dim3(kBlock), 0, st, in, out, outer, inner, Dv1,
+                           itw, P.tw_stride, P.d_pc, den);
+      else if (Nv == 128)
+        hipLaunchKernelGGL(intt_reg_kernel<16>, g, dim3(kBlock), 0, st, in, out, outer, inner,
+                           Dv1, itw, P.tw_stride, P.d_pc, den);
+      else
+        hipLaunchKernelGGL(intt_reg_kernel<32>, g, dim3(kBlock), 0, st, in, out, outer, inner,
+                           Dv1, itw, P.tw_stride, P.d_pc, den);
       hipError_t err = hipGetLastError();
       if (err != hipSuccess) return err;
       in = out;
