@@ -97,7 +97,10 @@ typedef struct polydet_shape {
  * captured solve stays one graph), so that one chunk's memory-bound passes overlap the next
  * chunk's elimination. With the environment variable POLYDET_BATCH_STREAMS = 1 (read when the
  * plan is made) every launch runs on the caller's stream, in chunks of the whole budget.
- * Plans made with POLYDET_STAGE_TIMING run every launch on the caller's stream. */
+ * Plans made with POLYDET_STAGE_TIMING run every launch on the caller's stream.
+ * Interpolation passes of 32 to 256 points along a contiguous axis take their transform in
+ * registers (one LDS exchange per pass); the environment variable POLYDET_INTT_REGISTERS = 0,
+ * read once per process, keeps every pass in the LDS-staged form. Results are identical. */
 /* Plan flags. POLYDET_FORCE_PN(x): use exactly x primes (x >= the number the bound needs,
  * else EINVAL). POLYDET_PRIME_OFFSET(x): skip the first x primes of the table (a disjoint
  * prime set; the result does not depend on it). */
