@@ -375,6 +375,19 @@ def test_folded_reduction_and_reconstruction(n, deg, amp, seed, force):
     check_against_stages(arr, pl, ref)
 
 
+# interpolation passes in registers: 32 points over 32 lines (the 4 x 8 form), 128 points over
+# 64 (16 x 8, with a first variable of 14 coefficients: the term-by-term evaluation), 64
+# points over 512 followed by a 32-point pass over 16 lines (LDS-staged)
+REG_CASES = [(6, (4, 3), 51), (5, (13, 8), 52), (4, (9, 4, 2), 53)]
+
+
+@pytest.mark.parametrize("n,deg,seed", REG_CASES)
+def test_register_form_interpolation_lengths(n, deg, seed):
+    arr = W.random_matrix(np.random.default_rng(seed), n, deg, -50, 50, zero_prob=0.2)
+    got, pl, _ = gpu_solve(arr)
+    assert box_to_dict(got) == box_to_dict(oracle_box(arr))
+
+
 def test_reconstruction_tiles_beyond_lds():
     # 28 primes over a last-variable grid of 256: the folded pass's tiles (28 x 384 words) do
     # not fit its LDS, so the last pass and the reconstruction run as separate launches; the
