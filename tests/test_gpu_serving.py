@@ -90,7 +90,9 @@ def test_chunked_jobs_equal_alone():
 
 def test_cancel_waiting_and_running_jobs():
     from concurrent.futures import CancelledError
-    big = W.config2()
+    # the job cancelled while running: 28 primes of a 256^3 grid, run one prime at a time
+    # (tens of ms each), so it is still running when the cancel comes
+    big = W.random_matrix(np.random.default_rng(7), 32, (5, 5, 5), -65536, 65536)
     smalls = small_jobs(12, 4)
     srv = S.Server(memory_budget=8 << 30, slots=1, prime_chunk=1)
     f_big = srv.submit(big)
@@ -99,7 +101,7 @@ def test_cancel_waiting_and_running_jobs():
     assert srv.cancel(f_small[-1])
     with pytest.raises(CancelledError):
         f_small[-1].result(timeout=5)
-    assert srv.cancel(f_big)  # running (or about to start): stops at a prime boundary
+    assert srv.cancel(f_big)  # running: stops at its next prime boundary
     with pytest.raises(CancelledError):
         f_big.result(timeout=60)
     for a, f in zip(smalls[:-1], f_small[:-1]):
