@@ -458,7 +458,8 @@ def bench_batch(args):
                      "frac_of_single_step_peak": achieved / (SINGLE_STEP_PEAK_UPDATES / 1e12),
                      "traffic": None,
                      "kernel": "det_fused(_pair)_batch_kernel<n,lanes>: every elimination "
-                               "launch of one batched solve",
+                               "launch of one batched solve (order 24, 4 lanes, two terms per "
+                               "lane: det_fused_pair_kernel<24,4,2> once per matrix)",
                      "work_per_launch": updates, "avg_ms": det_ms,
                      "avg_ms_source": "HIP events before and after each elimination launch of "
                                       "one batched solve (sum)"},

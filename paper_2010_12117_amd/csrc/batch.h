@@ -78,6 +78,8 @@ struct BLaunch {
   int32_t ll;          // elimination launches: left-looking form (lanes = 1) or repair pass
   int32_t pair;        // elimination launches: terms per lane of the paired first-variable
                        // evaluation (fused_pair_terms), 0 when unpaired
+  int32_t each;        // elimination launches: one single-matrix launch per descriptor in
+                       // place of the batched kernel (batch_det_each)
   int32_t pnmax;       // reconstruction launches: largest prime count
   int32_t chunk;       // the chunk of matrices the launch belongs to
   size_t lds;          // dynamic LDS per block
@@ -98,6 +100,11 @@ hipError_t batch_garner(const BGarner* desc, int ndesc, int64_t vblocks, int pnm
 // that many fused_pair_terms, or 0: none has.
 hipError_t batch_det(int n, int lanes, int ll, int pair, const BDet* desc, int ndesc,
                      int64_t vblocks, size_t lds, uint8_t* ws, hipStream_t st);
+// The same elimination as batch_det (ll = 0 or 2) as one launch of the single-matrix kernel
+// per matrix. `host_desc` is the host copy of the launch's descriptors; the kernels read the
+// workspace `ws` on the device.
+hipError_t batch_det_each(int n, int lanes, bool fixup, const BDet* host_desc, int ndesc,
+                          int64_t vblocks, uint8_t* ws, hipStream_t st);
 
 template <int N, int GL>
 hipError_t det_fused_batch_launch(const BDet* desc, int ndesc, int64_t vblocks, size_t lds,

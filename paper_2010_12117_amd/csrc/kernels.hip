@@ -997,6 +997,40 @@ struct BatchDet {
   }
 };
 
+// The batched elimination's matrices one by one: matrix i's primes are the virtual blocks from
+// its block0 to the next descriptor's, rtiles * jtiles per prime.
+template <int N, int GL>
+struct EachDet {
+  static hipError_t run(bool fixup, const BDet* desc, int ndesc, int64_t vblocks, uint8_t* ws,
+                        hipStream_t st) {
+    for (int i = 0; i < ndesc; ++i) {
+      const BDet& d = desc[i];
+      const int64_t end = i + 1 < ndesc ? desc[i + 1].block0 : vblocks;
+      FusedDetArgs f;
+      f.pre = (const uint32_t*)(ws + d.pre_off);
+      f.detv = (uint32_t*)(ws + d.detv_off);
+      f.denv = (uint32_t*)(ws + d.den_off);
+      f.R = f.Rout = f.seg = d.R;
+      f.off1 = f.off2 = 0;
+      f.N0 = d.N0;
+      f.m0 = d.m0;
+      f.Q = d.Q;
+      f.S = d.S;
+      f.tw0 = d.tw0;
+      f.tw_stride = d.tw_stride;
+      f.pcs = d.pc;
+      f.zero = d.zero;
+      f.slot = d.slot;
+      f.nslot = d.nslot;
+      f.pn = (int)((end - d.block0) / (d.rtiles * d.jtiles));
+      f.fixup = fixup;
+      const hipError_t e = det_fused_launch<N, GL>(f, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+};
+
 // Calls F<N, GL>::run(args...) for the (order, lanes) pair if a kernel is compiled for it.
 template <template <int, int> class F, int N, typename... A>
 hipError_t det_dispatch_n(int lanes, A&&... args) {
@@ -1335,6 +1369,11 @@ hipError_t batch_garner(const BGarner* desc, int ndesc, int64_t vblocks, int pnm
 hipError_t batch_det(int n, int lanes, int ll, int pair, const BDet* desc, int ndesc,
                      int64_t vblocks, size_t lds, uint8_t* ws, hipStream_t st) {
   return det_dispatch<BatchDet>(n, lanes, ll, pair, desc, ndesc, vblocks, lds, ws, st);
+}
+
+hipError_t batch_det_each(int n, int lanes, bool fixup, const BDet* host_desc, int ndesc,
+                          int64_t vblocks, uint8_t* ws, hipStream_t st) {
+  return det_dispatch<EachDet>(n, lanes, fixup, host_desc, ndesc, vblocks, ws, st);
 }
 
 }  // namespace pd

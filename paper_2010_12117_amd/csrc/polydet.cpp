@@ -576,8 +576,14 @@ static polydet_status run_batched(polydet_plan_t plan, const int64_t* d_coeffs,
         e = pd::batch_expand((const pd::BExpand*)desc, L.ndesc, L.vblocks, ws, ls);
         break;
       case pd::BLaunch::kDet:
-        e = pd::batch_det(L.n, L.lanes, L.ll, L.pair, (const pd::BDet*)desc, L.ndesc,
-                          L.vblocks, L.lds, ws, ls);
+        if (L.each) {
+          e = pd::batch_det_each(L.n, L.lanes, L.ll == 2,
+                                 (const pd::BDet*)(B->bp.desc_blob.data() + L.desc_off), L.ndesc,
+                                 L.vblocks, ws, ls);
+        } else {
+          e = pd::batch_det(L.n, L.lanes, L.ll, L.pair, (const pd::BDet*)desc, L.ndesc,
+                            L.vblocks, L.lds, ws, ls);
+        }
         break;
       case pd::BLaunch::kIntt:
         e = pd::batch_intt((const pd::BIntt*)desc, L.ndesc, L.vblocks, L.lds, ws, ls);
