@@ -266,6 +266,10 @@ constexpr int det_waves() {
   // 4 lanes from order 21: the kernels land at 164-187 VGPRs (2 waves); asked for 3 they spill
   // up to 14 values and ran the 4096-matrix batch 5% faster, batched and plain alike
   if (GL == 4 && N >= 21) return 3;
+  // 2 lanes at orders 13 and 16 (133-135 and 176-178 VGPRs unasked: 3 and 2 waves): asked for 4
+  // and 3 they spill 7-11 values and ran those classes of the batch 4% and 7-11% faster
+  if (GL == 2 && N == 16) return 3;
+  if (GL == 2 && N == 13) return 4;
   if (GL != 1 || !PAIR) return 1;
   constexpr int regs = ((N * N + kDetRegMargin + 7) / 8) * 8;
   constexpr int w = 512 / regs;
